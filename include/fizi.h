@@ -1,0 +1,194 @@
+/*
+ * fizi.h - C ABI of the MI355X (gfx950) FIZI/Mouse pipeline: the per-frame
+ * pixel path of Magoules & Zou, "GPU Accelerated Contactless Human Machine
+ * Interface for Driving Car" (arXiv 1907.04393).
+ *
+ * What the path computes (paper Section 2, "Architecture"; Section 3.1,
+ * "Building the Mask of the Hand"; Section 3.2, "Managing Luminosity"):
+ *   initialisation: learn the background from user-free frames;
+ *   running phase, per frame: correct the brightness, keep the pixels that
+ *   are (i) outside the learned background range, (ii) not gray and (iii) of
+ *   skin hue, AND the three masks, clean the result with erosion and dilation
+ *   (the binary image I_FIZI), pick the hand zone, and reduce it to a pointer
+ *   (position sums, area, bounding box and a click state).
+ * The readings taken where the paper is silent or garbled are stated at each
+ * parameter below.
+ *
+ * Conventions
+ *   - Every d_* pointer is a DEVICE pointer owned by the caller; h_* pointers
+ *     are host memory. The library never frees caller memory and never calls
+ *     hipMalloc: device state lives in a caller-provided block (d_state).
+ *     It allocates a little pinned host memory and a few HIP events at
+ *     create time only.
+ *   - Frames are H x W x 3 uint8, R,G,B interleaved, row-major, contiguous;
+ *     n frames are n consecutive frames. W must be a positive multiple of 64
+ *     (so each mask row is a whole number of 64-bit words), H >= 1, and
+ *     W * H < 2^31.
+ *   - Bit masks are H rows of W/64 uint64 words; bit b of word j of row y is
+ *     pixel (x = 64 j + b, y) (LSB first).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls marked async only enqueue work on it.
+ *   - Return value: FIZI_OK (0) or a negative FIZI_E* code; the message of
+ *     the last failure on the calling thread is in fizi_last_error(). No C++
+ *     exception crosses this boundary, and a failed call leaves its context
+ *     usable.
+ *   - A context or batch is used from one host thread at a time.
+ */
+#ifndef FIZI_H
+#define FIZI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FIZI_OK = 0,
+    FIZI_EINVAL = -1,   /* bad geometry, parameter, pointer or size */
+    FIZI_ESTATE = -2,   /* e.g. process_frames before any learn_background */
+    FIZI_ENOMEM = -3,   /* state block too small, or pinned host memory */
+    FIZI_EHIP = -4,     /* HIP runtime error (message has the HIP string) */
+    FIZI_ERANGE = -5    /* frame index not (or no longer) available */
+};
+
+typedef struct {
+    int32_t width;      /* W: multiple of 64, >= 64 */
+    int32_t height;     /* H: >= 1 */
+} fizi_geom;
+
+/* Thresholds and readings. fizi_default_params() fills the defaults. */
+typedef struct {
+    /* Section 3.1 (iii): skin when chroma > 0 and the exact hexcone hue lies
+     * in the closed interval [alpha1, alpha2] (centi-degrees, 0..35999),
+     * wrapping through 360 when alpha1 > alpha2. Defaults 33000, 7500 (the
+     * paper's own values are lost with its Figure 2). */
+    int32_t alpha1_cdeg;
+    int32_t alpha2_cdeg;
+    /* Section 3.1 (ii): gray when max_RGB - min_RGB < S. 0..255, default 20. */
+    int32_t gray_S;
+    /* Section 3.1 (i): background when every channel lies in
+     * [bgmin - delta, bgmax + delta]. 0..255, default 10 (0 = the bare box). */
+    int32_t bg_delta;
+    /* Section 3.1, last paragraph: opening (erosions then dilations) then
+     * closing (dilations then erosions), 3x3 square, out-of-image pixels
+     * neutral (1 for erosion, 0 for dilation). 0..3 each, default 1, 1. */
+    int32_t open_iters;
+    int32_t close_iters;
+    /* Section 2, Mouse module: the hand zone is the 8-connected component of
+     * largest area (ties: smallest first raster index); present when its
+     * area >= min_area (>= 0, default 1). */
+    int32_t min_area;
+    /* Section 2 "its state (click or not)": click when
+     * 1000 * area >= click_fill_permille * bbox_area. 0..1000, default 700. */
+    int32_t click_fill_permille;
+    /* Section 2 / 3.2 brightness: one global inverse gain per frame, Q16, from
+     * the luminance R+2G+B of rows y % gain_row_stride == 0 against the first
+     * learning frame, over pixels whose reference is unclipped, whose raw
+     * channels are all in 1..254 and whose raw hue is not skin; rounded half
+     * up and clamped to [gain_lo_q16, gain_hi_q16]. Each channel becomes
+     * min(255, (v * inv + 32768) >> 16). Defaults 8, 32768, 131072. */
+    int32_t gain_row_stride;   /* 1..64 */
+    int32_t gain_lo_q16;       /* 1..2^20 */
+    int32_t gain_hi_q16;       /* gain_lo_q16..2^20 */
+} fizi_params;
+
+/* One frame's pointer (56 bytes). When `present` is 0 every field except
+ * n_components, inv_gain_q16 and frame_index is zero. The centroid is
+ * (sum_x / area, sum_y / area); x is the column, y the row. */
+typedef struct {
+    uint8_t present;
+    uint8_t click;
+    uint16_t reserved;
+    uint32_t area;
+    uint64_t sum_x;
+    uint64_t sum_y;
+    uint32_t x0, y0, x1, y1;     /* inclusive bounding box */
+    uint32_t n_components;       /* 8-connected components of I_FIZI */
+    uint32_t inv_gain_q16;       /* the frame's inverse gain */
+    uint64_t frame_index;        /* running index within the context */
+} fizi_pointer;
+
+typedef struct fizi_ctx fizi_ctx;
+
+/* Byte offsets of the learned model inside a context's state block. */
+typedef struct {
+    uint64_t bgmin;        /* H*W*3 uint8, frame layout */
+    uint64_t bgmax;        /* H*W*3 uint8 */
+    uint64_t yref;         /* yref_rows * W uint16: reference luminance of the
+                              sampled rows, 0xFFFF where a channel was clipped */
+    uint64_t yref_rows;    /* ceil(H / gain_row_stride) */
+    uint64_t total;        /* == fizi_state_bytes() */
+} fizi_layout;
+
+/* Fills *out with the defaults listed above. */
+int fizi_default_params(fizi_params *out);
+
+/* Checks geometry and parameters (FIZI_EINVAL with a message, else 0). */
+int fizi_validate(const fizi_geom *geom, const fizi_params *params);
+
+/* Device bytes a context needs when it processes up to `chunk_frames`
+ * frames per internal batch (1..256). 0 when the arguments are invalid. */
+size_t fizi_state_bytes(const fizi_geom *geom, const fizi_params *params, int32_t chunk_frames);
+
+/* Offsets of the model arrays inside the state block. */
+int fizi_state_layout(const fizi_geom *geom, const fizi_params *params, int32_t chunk_frames,
+                      fizi_layout *out);
+
+/* Creates a context over the caller's device block d_state (256-byte
+ * aligned, >= fizi_state_bytes; kept by the caller until fizi_destroy).
+ * Enqueues the block's initialisation on `stream`. */
+int fizi_create(const fizi_geom *geom, const fizi_params *params, int32_t chunk_frames,
+                void *d_state, size_t state_bytes, void *stream, fizi_ctx **out);
+
+/* Section 2 initialisation ("learns the background without the user") with
+ * the model of Section 3.1 (i): with reset != 0 the reference luminance is
+ * taken from d_frames[0] and the per-pixel, per-channel [bgmin, bgmax] model
+ * starts empty; otherwise learning continues from the current model. Each
+ * frame is brightness-corrected (as in process_frames) before it widens the
+ * model; the model is read and written once per call. n_frames >= 1. Async. */
+int learn_background(fizi_ctx *ctx, const uint8_t *d_frames, int32_t n_frames, int32_t reset,
+                     void *stream);
+
+/* Section 2 running phase for n_frames >= 1 frames: brightness correction,
+ * the masks I_R1, I_R2, I_R3 of Section 3.1 and their AND, opening and
+ * closing (I_FIZI), the hand zone and its pointer. Frames are independent
+ * given the model and are processed in internal batches of chunk_frames.
+ * d_fizi_bits (nullable): n_frames bit masks of I_FIZI. d_hand_bits
+ * (nullable): n_frames bit masks of the selected hand zone. d_pointers
+ * (nullable): n_frames pointers. Frame indices continue from the previous
+ * call. FIZI_ESTATE before the first learn_background. Async. */
+int process_frames(fizi_ctx *ctx, const uint8_t *d_frames, int32_t n_frames,
+                   uint64_t *d_fizi_bits, uint64_t *d_hand_bits, fizi_pointer *d_pointers,
+                   void *stream);
+
+/* Waits for the frame with running index frame_index and copies its pointer
+ * to *h_out. The last 65536 frames are kept; older or not yet submitted
+ * indices give FIZI_ERANGE. */
+int get_pointer(fizi_ctx *ctx, int64_t frame_index, fizi_pointer *h_out);
+
+/* Waits for the context's work, releases its host resources. Frees nothing
+ * the caller owns. */
+int fizi_destroy(fizi_ctx *ctx);
+
+/* Measurement hook. With enable != 0 the context records a HIP event pair
+ * on the call's stream around each launch of the stages below (at most
+ * 16384 launches per stage between two reads); fizi_stage_times() waits for
+ * them, returns the summed milliseconds and launch counts per stage, and
+ * clears them. Stages: 0 gain, 1 classify, 2 morphology, 3 components and
+ * pointer, 4 background learning. */
+enum { FIZI_STAGE_GAIN = 0, FIZI_STAGE_CLASSIFY, FIZI_STAGE_MORPH, FIZI_STAGE_RESOLVE,
+       FIZI_STAGE_LEARN, FIZI_NSTAGES };
+int fizi_stage_timing(fizi_ctx *ctx, int32_t enable);
+int fizi_stage_times(fizi_ctx *ctx, double *h_ms /* [FIZI_NSTAGES] */,
+                     int64_t *h_launches /* [FIZI_NSTAGES] */);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fizi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIZI_H */

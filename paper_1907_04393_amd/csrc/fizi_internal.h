@@ -1,0 +1,107 @@
+// Internal layout shared by the HIP kernels and the C-ABI host code.
+//
+// Work is described by a job table in device memory: one Job per frame to
+// process (a frame of a context's stream, or a learning frame), with the
+// pointers to its inputs, outputs and scratch, its geometry and thresholds,
+// and a few accumulators the kernels update atomically. The host fills the
+// table in pinned memory and copies it to the device ahead of the kernels,
+// which also zeroes the accumulators for that call. Every kernel walks a flat
+// list of tiles (grid-stride) and finds a tile's job by binary search in a
+// prefix array, so one launch covers frames of any mix of resolutions and a
+// launch's shape does not depend on the work it is given.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fizi.h"
+
+namespace fizi {
+
+constexpr int kMaxJobs = 256;          // jobs per table
+constexpr uint16_t kYrefClipped = 0xFFFFu;
+constexpr int kMaxMorphIters = 3;      // open_iters, close_iters <= 3
+
+// Skin-hue test on one RGB triple, without division (Section 3.1 (iii)).
+// For a hue a, let d_a be an RGB colour of hue a. The determinant
+// D(a, p) = det[(1,1,1), d_a, p] = kr (R - B) + kg (G - B) is positive exactly
+// when the hue of p lies in the open half-turn (a, a + 180) and zero when it
+// is a or a + 180, because the hexcone hue is a monotone, odd-symmetric
+// re-parametrisation of the angle around the gray axis. The closed interval
+// [a1, a2] of length L is then
+//   L = 0:        D1 == 0 and p points along d_a1 (3 d.p - sum(d) sum(p) > 0)
+//   0 < L < 180:  D1 >= 0 and D2 <= 0
+//   L = 180:      D1 >= 0
+//   L > 180:      D1 >= 0 or D2 <= 0
+// always together with chroma > 0.
+struct HueTest {
+    int32_t k1r, k1g;          // D(a1, p) coefficients
+    int32_t k2r, k2g;          // D(a2, p) coefficients
+    int32_t dr, dg, db, dsum;  // d_a1 (scaled by 6000) for the one-point case
+    int32_t mode;              // 0: L = 0, 1: 0 < L < 180, 2: L = 180, 3: L > 180
+    int32_t pad;
+};
+
+struct Job {
+    const uint8_t *frame;      // H*W*3
+    const uint8_t *bgmin;      // H*W*3
+    const uint8_t *bgmax;      // H*W*3
+    const uint16_t *yref;      // ceil(H/rs) * W
+    uint64_t *raw;             // H*Wd words: AND of the three masks
+    uint64_t *fizi;            // H*Wd words: after opening and closing
+    uint64_t *hand;            // H*Wd words or null
+    uint32_t *parent;          // W*H: union-find parent, valid at run starts
+    uint32_t *area;            // W*H: component area, valid at roots
+    uint2 *runs;               // run_cap runs (start pixel, length)
+    fizi_pointer *out;         // one pointer
+    uint64_t frame_index;
+    int32_t W, H, Wd, rs;
+    uint32_t run_cap;
+    int32_t delta, S1, open_it, close_it, min_area, fill_pm, glo, ghi;
+    HueTest hue;
+    // accumulators (zero when the table is uploaded)
+    unsigned long long num, den;
+    uint32_t done, inv, nruns, flags;
+};
+
+struct TableHeader {
+    int32_t njobs;
+    int32_t pad0;
+    int32_t gain_pre[kMaxJobs + 1];   // sampled-row tiles
+    int32_t cls_pre[kMaxJobs + 1];    // classify tiles
+    int32_t mor_pre[kMaxJobs + 1];    // morphology bands
+    int32_t pad1;
+};
+
+struct Table {
+    TableHeader h;
+    Job jobs[kMaxJobs];
+};
+
+static_assert(sizeof(TableHeader) % 8 == 0, "job array alignment");
+
+// Launch shapes (tunable per resolution class).
+struct Tuning {
+    int cls_iters;      // classify tile = 1024 * cls_iters pixels (1, 2, 4, 8)
+    int morph_rows;     // morphology band height (16, 32, 64)
+    int grid_per_cu;    // resident blocks per CU for the streaming kernels
+};
+
+inline int cls_tile_px(const Tuning &t) { return 1024 * t.cls_iters; }
+
+// Kernel launchers (fizi_kernels.hip). Each returns the hipError_t of its launch.
+hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H, int rs,
+                            hipStream_t s);
+hipError_t launch_gain(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t,
+                       hipStream_t s);
+hipError_t launch_minmax(const Table *d_tab, int njobs, uint8_t *bgmin, uint8_t *bgmax,
+                         int npx, int reset, int n_cu, hipStream_t s);
+hipError_t launch_classify(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t,
+                           hipStream_t s);
+hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max_ops, int n_cu,
+                        const Tuning &t, hipStream_t s);
+hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+
+}  // namespace fizi

@@ -1,0 +1,771 @@
+// HIP kernels of the FIZI/Mouse pipeline for gfx950 (CDNA4, wave64).
+//
+//   k_make_yref  reference luminance of the sampled rows of the first
+//                learning frame (Section 2 initialisation, Section 3.2)
+//   k_gain       per-frame inverse gain from the sampled rows; the last block
+//                of each frame turns the two sums into the Q16 gain
+//   k_minmax     background learning: per-pixel, per-channel min/max of the
+//                gain-corrected frames, model read and written once
+//                (Section 3.1 (i))
+//   k_classify   gain correction, I_R1 (outside the learned box), I_R2 (not
+//                gray), I_R3 (skin hue), their AND, packed to bits with wave
+//                ballots (Section 3.1); HBM-bound, 4 pixels per lane
+//   k_morph      opening then closing with a 3x3 square on an LDS band of bit
+//                rows (64 pixels per operation), then run extraction
+//                (Section 3.1, last paragraph)
+//   k_resolve    8-connected components by union-find over runs, hand-zone
+//                selection and the pointer (Section 2, Mouse module)
+#include "fizi_internal.h"
+
+namespace fizi {
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int find_job(const int32_t *pre, int nj, int t)
+{
+    int lo = 0, hi = nj - 1;          // largest j with pre[j] <= t
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Brightness correction of one channel value (Q16 inverse gain, half up,
+// saturated).
+__device__ __forceinline__ uint32_t corr(uint32_t v, uint32_t inv)
+{
+    uint32_t t = (v * inv + 32768u) >> 16;
+    return t < 255u ? t : 255u;
+}
+
+// Skin-hue membership without division; see HueTest. Chroma > 0 is checked
+// by the caller.
+__device__ __forceinline__ bool hue_in(int r, int g, int b, const HueTest &h)
+{
+    const int rb = r - b, gb = g - b;
+    const int d1 = h.k1r * rb + h.k1g * gb;
+    if (h.mode == 1)
+        return (d1 >= 0) & (h.k2r * rb + h.k2g * gb <= 0);
+    if (h.mode == 3)
+        return (d1 >= 0) | (h.k2r * rb + h.k2g * gb <= 0);
+    if (h.mode == 2)
+        return d1 >= 0;
+    return (d1 == 0) & (3 * (h.dr * r + h.dg * g + h.db * b) - h.dsum * (r + g + b) > 0);
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w0, uint32_t w1, uint32_t w2, int i)
+{
+    const uint32_t w = i < 4 ? w0 : (i < 8 ? w1 : w2);
+    return (w >> (8 * (i & 3))) & 0xFFu;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Spreads the low 16 bits of x so that bit t lands on bit 4t.
+__device__ __forceinline__ uint64_t spread4(uint64_t x)
+{
+    x &= 0xFFFFull;
+    x = (x | (x << 24)) & 0x000000FF000000FFull;
+    x = (x | (x << 12)) & 0x000F000F000F000Full;
+    x = (x | (x << 6)) & 0x0303030303030303ull;
+    x = (x | (x << 3)) & 0x1111111111111111ull;
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_make_yref(const uint8_t *__restrict__ frame0,
+                                                   uint16_t *__restrict__ yref, int W, int H,
+                                                   int rs)
+{
+    const int rows = (H + rs - 1) / rs;
+    const int groups = W / 4;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rows * groups;
+         i += gridDim.x * blockDim.x) {
+        const int rr = i / groups, g = i - rr * groups;
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(frame0 + (size_t)rr * rs * W * 3) + 3 * g;
+        const uint32_t w0 = p[0], w1 = p[1], w2 = p[2];
+        uint32_t out[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = byte_of(w0, w1, w2, 3 * k), gg = byte_of(w0, w1, w2, 3 * k + 1),
+                           b = byte_of(w0, w1, w2, 3 * k + 2);
+            const bool ok = (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
+            out[k] = ok ? r + 2 * gg + b : kYrefClipped;
+        }
+        uint2 v;
+        v.x = out[0] | (out[1] << 16);
+        v.y = out[2] | (out[3] << 16);
+        reinterpret_cast<uint2 *>(yref + (size_t)rr * W)[g] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gain(Table *__restrict__ T)
+{
+    __shared__ uint32_t s_num[256 / kWave], s_den[256 / kWave];
+    const int nj = T->h.njobs;
+    const int total = T->h.gain_pre[nj];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int j = find_job(T->h.gain_pre, nj, t);
+        Job *J = &T->jobs[j];
+        const int rr = t - T->h.gain_pre[j];
+        const int W = J->W;
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(J->frame + (size_t)rr * J->rs * W * 3);
+        const uint2 *yr = reinterpret_cast<const uint2 *>(J->yref + (size_t)rr * W);
+        const HueTest h = J->hue;
+        uint32_t num = 0, den = 0;
+        for (int g = threadIdx.x; g < W / 4; g += blockDim.x) {
+            const uint32_t w0 = row[3 * g], w1 = row[3 * g + 1], w2 = row[3 * g + 2];
+            const uint2 yv = yr[g];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t r = byte_of(w0, w1, w2, 3 * k), gg = byte_of(w0, w1, w2, 3 * k + 1),
+                               b = byte_of(w0, w1, w2, 3 * k + 2);
+                const uint32_t y = ((k < 2 ? yv.x : yv.y) >> (16 * (k & 1))) & 0xFFFFu;
+                bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
+                if (ok) {
+                    const int mx = max(max((int)r, (int)gg), (int)b);
+                    const int mn = min(min((int)r, (int)gg), (int)b);
+                    if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
+                        ok = false;
+                }
+                if (ok) {
+                    num += y;
+                    den += r + 2 * gg + b;
+                }
+            }
+        }
+        num = wave_sum(num);
+        den = wave_sum(den);
+        if (lane == 0) {
+            s_num[wave] = num;
+            s_den[wave] = den;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long n = 0, d = 0;
+            for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+                n += s_num[w];
+                d += s_den[w];
+            }
+            atomicAdd(&J->num, n);
+            atomicAdd(&J->den, d);
+            __threadfence();
+            const uint32_t tiles = (uint32_t)(T->h.gain_pre[j + 1] - T->h.gain_pre[j]);
+            const uint32_t prev = atomicAdd(&J->done, 1u);
+            if (prev == tiles - 1) {
+                __threadfence();
+                const unsigned long long N = __hip_atomic_load(&J->num, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long D = __hip_atomic_load(&J->den, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t inv = 65536u;
+                if (D != 0) {
+                    unsigned long long q = (N * 65536ull + D / 2) / D;
+                    if (q < (unsigned long long)J->glo) q = (unsigned long long)J->glo;
+                    if (q > (unsigned long long)J->ghi) q = (unsigned long long)J->ghi;
+                    inv = (uint32_t)q;
+                }
+                __hip_atomic_store(&J->inv, inv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_minmax(Table *__restrict__ T, int nj,
+                                                uint8_t *__restrict__ bgmin,
+                                                uint8_t *__restrict__ bgmax, int npx, int reset)
+{
+    const int ngroups = npx / 4;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += gridDim.x * blockDim.x) {
+        uint32_t *pmin = reinterpret_cast<uint32_t *>(bgmin) + 3 * g;
+        uint32_t *pmax = reinterpret_cast<uint32_t *>(bgmax) + 3 * g;
+        uint32_t lo[12], hi[12];
+        if (reset) {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) {
+                lo[i] = 255u;
+                hi[i] = 0u;
+            }
+        } else {
+            const uint32_t a0 = pmin[0], a1 = pmin[1], a2 = pmin[2];
+            const uint32_t b0 = pmax[0], b1 = pmax[1], b2 = pmax[2];
+#pragma unroll
+            for (int i = 0; i < 12; ++i) {
+                lo[i] = byte_of(a0, a1, a2, i);
+                hi[i] = byte_of(b0, b1, b2, i);
+            }
+        }
+        for (int j = 0; j < nj; ++j) {
+            const uint32_t *f = reinterpret_cast<const uint32_t *>(T->jobs[j].frame) + 3 * g;
+            const uint32_t inv = T->jobs[j].inv;
+            const uint32_t w0 = f[0], w1 = f[1], w2 = f[2];
+#pragma unroll
+            for (int i = 0; i < 12; ++i) {
+                const uint32_t v = corr(byte_of(w0, w1, w2, i), inv);
+                lo[i] = min(lo[i], v);
+                hi[i] = max(hi[i], v);
+            }
+        }
+        uint32_t a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            a[i >> 2] |= lo[i] << (8 * (i & 3));
+            b[i >> 2] |= hi[i] << (8 * (i & 3));
+        }
+        pmin[0] = a[0];
+        pmin[1] = a[1];
+        pmin[2] = a[2];
+        pmax[0] = b[0];
+        pmax[1] = b[1];
+        pmax[2] = b[2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One lane classifies 4 consecutive pixels (12 bytes of frame, 12 of bgmin,
+// 12 of bgmax); a wave covers 256 pixels = 4 mask words. The hue and gray
+// tests only run for pixels already outside the background box, so waves of
+// pure background skip them.
+template <int ITERS>
+__global__ __launch_bounds__(256) void k_classify(Table *__restrict__ T)
+{
+    const int nj = T->h.njobs;
+    const int total = T->h.cls_pre[nj];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int j = find_job(T->h.cls_pre, nj, t);
+        const Job *J = &T->jobs[j];
+        const int tile = t - T->h.cls_pre[j];
+        const uint32_t npx = (uint32_t)J->W * (uint32_t)J->H;
+        const uint32_t inv = J->inv;
+        const int delta = J->delta, S1 = J->S1;
+        const HueTest h = J->hue;
+        const uint32_t *fr = reinterpret_cast<const uint32_t *>(J->frame);
+        const uint32_t *mnp = reinterpret_cast<const uint32_t *>(J->bgmin);
+        const uint32_t *mxp = reinterpret_cast<const uint32_t *>(J->bgmax);
+        uint64_t *raw = J->raw;
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it) {
+            const uint32_t base = ((uint32_t)tile * ITERS + it) * 1024u + (uint32_t)wave * 256u;
+            if (base >= npx)
+                break;
+            const uint32_t p = base + 4u * lane;
+            uint32_t bits = 0;
+            if (p < npx) {
+                const uint32_t q = 3u * (p >> 2);
+                const uint32_t f0 = fr[q], f1 = fr[q + 1], f2 = fr[q + 2];
+                const uint32_t l0 = mnp[q], l1 = mnp[q + 1], l2 = mnp[q + 2];
+                const uint32_t u0 = mxp[q], u1 = mxp[q + 1], u2 = mxp[q + 2];
+                int cv[12];
+                uint32_t out = 0;
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    const int v = (int)corr(byte_of(f0, f1, f2, i), inv);
+                    const int lo = (int)byte_of(l0, l1, l2, i) - delta;
+                    const int hi = (int)byte_of(u0, u1, u2, i) + delta;
+                    cv[i] = v;
+                    out |= (uint32_t)((v < lo) | (v > hi)) << (i / 3);
+                }
+                if (out) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (out & (1u << k)) {
+                            const int r = cv[3 * k], g = cv[3 * k + 1], b = cv[3 * k + 2];
+                            const int c = max(max(r, g), b) - min(min(r, g), b);
+                            if (c >= S1 && hue_in(r, g, b, h))
+                                bits |= 1u << k;
+                        }
+                    }
+                }
+            }
+            const uint64_t b0 = __ballot(bits & 1u), b1 = __ballot(bits & 2u),
+                           b2 = __ballot(bits & 4u), b3 = __ballot(bits & 8u);
+            if (lane < 4) {
+                const uint32_t word = (base >> 6) + lane;
+                const int sh = 16 * lane;
+                if (word < (npx >> 6))
+                    raw[word] = spread4(b0 >> sh) | (spread4(b1 >> sh) << 1) |
+                                (spread4(b2 >> sh) << 2) | (spread4(b3 >> sh) << 3);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive block scan of one uint32 per thread (blockDim.x = 256).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_wave, uint32_t *total)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == kWave - 1)
+        s_wave[wave] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+        const uint32_t s = s_wave[w];
+        if (w < wave)
+            off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+// Last pixel (x) of the run of ones that starts at bit b of word w of a row.
+__device__ __forceinline__ int run_end_lds(const uint64_t *row, int Wd, int w, int b)
+{
+    uint64_t word = row[w];
+    uint64_t nxt = (w + 1 < Wd) ? row[w + 1] : 0ull;
+    uint64_t ends = (word & ~((word >> 1) | (nxt << 63))) & (~0ull << b);
+    while (!ends) {
+        ++w;
+        word = row[w];
+        nxt = (w + 1 < Wd) ? row[w + 1] : 0ull;
+        ends = word & ~((word >> 1) | (nxt << 63));
+    }
+    return 64 * w + __builtin_ctzll(ends);
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T, int buf_words)
+{
+    extern __shared__ uint64_t lds[];
+    __shared__ uint32_t s_wave[256 / kWave];
+    __shared__ uint32_t s_base;
+    const int nj = T->h.njobs;
+    const int total = T->h.mor_pre[nj];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int j = find_job(T->h.mor_pre, nj, t);
+        Job *J = &T->jobs[j];
+        const int band = t - T->h.mor_pre[j];
+        const int W = J->W, H = J->H, Wd = J->Wd;
+        const int oi = J->open_it, ci = J->close_it;
+        const int nops = 2 * (oi + ci);
+        const int y0 = band * R, y1 = min(y0 + R, H);
+        const int ya = max(0, y0 - nops), yb = min(H, y1 + nops);
+        uint64_t *A = lds, *B = lds + buf_words;
+        const uint64_t *src = J->raw + (size_t)ya * Wd;
+        for (int i = threadIdx.x; i < (yb - ya) * Wd; i += blockDim.x)
+            A[i] = src[i];
+        __syncthreads();
+        int va = ya, vb = yb;
+        for (int op = 0; op < nops; ++op) {
+            const bool ero = (op < oi) || (op >= 2 * oi + ci);
+            const uint64_t neutral = ero ? ~0ull : 0ull;
+            const int na = (va == 0) ? 0 : va + 1;
+            const int nb = (vb == H) ? H : vb - 1;
+            for (int i = threadIdx.x; i < (nb - na) * Wd; i += blockDim.x) {
+                const int r = na + i / Wd, w = i - (i / Wd) * Wd;
+                uint64_t v[3];
+#pragma unroll
+                for (int d = -1; d <= 1; ++d) {
+                    const int ww = w + d;
+                    uint64_t acc;
+                    if (ww < 0 || ww >= Wd) {
+                        acc = neutral;
+                    } else {
+                        const uint64_t up = (r - 1 >= 0) ? A[(r - 1 - ya) * Wd + ww] : neutral;
+                        const uint64_t mid = A[(r - ya) * Wd + ww];
+                        const uint64_t dn = (r + 1 < H) ? A[(r + 1 - ya) * Wd + ww] : neutral;
+                        acc = ero ? (up & mid & dn) : (up | mid | dn);
+                    }
+                    v[d + 1] = acc;
+                }
+                const uint64_t left = (v[1] << 1) | (v[0] >> 63);
+                const uint64_t right = (v[1] >> 1) | (v[2] << 63);
+                B[(r - ya) * Wd + w] = ero ? (v[1] & left & right) : (v[1] | left | right);
+            }
+            __syncthreads();
+            uint64_t *tmp = A;
+            A = B;
+            B = tmp;
+            va = na;
+            vb = nb;
+        }
+        // I_FIZI rows of the band
+        const uint64_t *fin = A + (size_t)(y0 - ya) * Wd;
+        uint64_t *dst = J->fizi + (size_t)y0 * Wd;
+        const int nwords = (y1 - y0) * Wd;
+        for (int i = threadIdx.x; i < nwords; i += blockDim.x)
+            dst[i] = fin[i];
+        // runs of the band: count, reserve, emit
+        uint32_t cnt = 0;
+        for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+            const int w = i % Wd;
+            const uint64_t word = fin[i];
+            const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
+            cnt += (uint32_t)__popcll(word & ~((word << 1) | (prev >> 63)));
+        }
+        uint32_t band_total;
+        uint32_t off = block_excl_scan(cnt, s_wave, &band_total);
+        if (threadIdx.x == 0)
+            s_base = band_total ? atomicAdd(&J->nruns, band_total) : 0u;
+        __syncthreads();
+        uint32_t idx = s_base + off;
+        const uint32_t cap = J->run_cap;
+        if (threadIdx.x == 0 && s_base + band_total > cap)
+            atomicOr(&J->flags, 1u);
+        for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+            const int rl = i / Wd, w = i - rl * Wd;
+            const uint64_t word = fin[i];
+            const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
+            uint64_t st = word & ~((word << 1) | (prev >> 63));
+            while (st) {
+                const int b = __builtin_ctzll(st);
+                st &= st - 1;
+                const int xs = 64 * w + b;
+                const int xe = run_end_lds(fin + (size_t)rl * Wd, Wd, w, b);
+                const uint32_t start = (uint32_t)(y0 + rl) * (uint32_t)W + (uint32_t)xs;
+                if (idx < cap) {
+                    J->runs[idx] = make_uint2(start, (uint32_t)(xe - xs + 1));
+                    J->parent[start] = start;
+                    J->area[start] = 0u;
+                }
+                ++idx;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ld_parent(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t find_root(uint32_t *parent, uint32_t x)
+{
+    uint32_t p = ld_parent(parent + x);
+    while (p != x) {
+        x = p;
+        p = ld_parent(parent + x);
+    }
+    return x;
+}
+
+// Union of the trees of a and b; the smaller label becomes the root, so the
+// root of a finished component is its first run start in raster order.
+__device__ __forceinline__ void unite(uint32_t *parent, uint32_t a, uint32_t b)
+{
+    for (;;) {
+        a = find_root(parent, a);
+        b = find_root(parent, b);
+        if (a == b)
+            return;
+        if (a > b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        const uint32_t old = atomicMin(parent + b, a);
+        if (old == b)
+            return;
+        b = old;
+    }
+}
+
+__device__ __forceinline__ int next_one(const uint64_t *row, int pos, int limit)
+{
+    int w = pos >> 6;
+    uint64_t m = row[w] & (~0ull << (pos & 63));
+    for (;;) {
+        if (m) {
+            const int x = (w << 6) + __builtin_ctzll(m);
+            return x <= limit ? x : -1;
+        }
+        ++w;
+        if ((w << 6) > limit)
+            return -1;
+        m = row[w];
+    }
+}
+
+__device__ __forceinline__ int prev_zero(const uint64_t *row, int pos)
+{
+    int w = pos >> 6;
+    const int b = pos & 63;
+    uint64_t m = ~row[w] & (b == 63 ? ~0ull : ((2ull << b) - 1ull));
+    while (!m) {
+        --w;
+        if (w < 0)
+            return -1;
+        m = ~row[w];
+    }
+    return (w << 6) + 63 - __builtin_clzll(m);
+}
+
+__device__ __forceinline__ int next_zero(const uint64_t *row, int Wd, int pos)
+{
+    int w = pos >> 6;
+    uint64_t m = ~row[w] & (~0ull << (pos & 63));
+    while (!m) {
+        ++w;
+        if (w >= Wd)
+            return Wd << 6;
+        m = ~row[w];
+    }
+    return (w << 6) + __builtin_ctzll(m);
+}
+
+constexpr int kResolveThreads = 512;
+constexpr int kResolveWaves = kResolveThreads / kWave;
+
+template <typename T, typename Op>
+__device__ __forceinline__ T block_reduce(T v, T *s, Op op)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1)
+        v = op(v, (T)__shfl_xor(v, o, kWave));
+    if (lane == 0)
+        s[wave] = v;
+    __syncthreads();
+    T r = s[0];
+    for (int w = 1; w < kResolveWaves; ++w)
+        r = op(r, s[w]);
+    __syncthreads();
+    return r;
+}
+
+struct OpAdd { template <typename T> __device__ T operator()(T a, T b) const { return a + b; } };
+struct OpMax { template <typename T> __device__ T operator()(T a, T b) const { return a > b ? a : b; } };
+struct OpMin { template <typename T> __device__ T operator()(T a, T b) const { return a < b ? a : b; } };
+
+__global__ __launch_bounds__(kResolveThreads) void k_resolve(Table *__restrict__ T)
+{
+    __shared__ unsigned long long s_u64[kResolveWaves];
+    __shared__ uint32_t s_u32[kResolveWaves];
+    const int nj = T->h.njobs;
+    for (int j = blockIdx.x; j < nj; j += gridDim.x) {
+        Job *J = &T->jobs[j];
+        const int W = J->W, H = J->H, Wd = J->Wd;
+        const uint32_t nr = min(J->nruns, J->run_cap);
+        const uint2 *runs = J->runs;
+        uint32_t *parent = J->parent;
+        uint32_t *area = J->area;
+        const uint64_t *fz = J->fizi;
+        uint64_t *hand = J->hand;
+        if (hand)
+            for (int i = threadIdx.x; i < H * Wd; i += blockDim.x)
+                hand[i] = 0ull;
+        // A: link every run to the runs it touches in the row above
+        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+            const uint2 rn = runs[i];
+            const int y = (int)(rn.x / (uint32_t)W);
+            if (y == 0)
+                continue;
+            const int xs = (int)(rn.x - (uint32_t)y * W), xe = xs + (int)rn.y - 1;
+            const uint64_t *above = fz + (size_t)(y - 1) * Wd;
+            const int hi = min(xe + 1, W - 1);
+            int pos = max(xs - 1, 0);
+            while (pos <= hi) {
+                const int xb = next_one(above, pos, hi);
+                if (xb < 0)
+                    break;
+                const int bs = prev_zero(above, xb) + 1;
+                unite(parent, rn.x, (uint32_t)(y - 1) * W + (uint32_t)bs);
+                pos = next_zero(above, Wd, xb) + 1;
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        // B: roots and areas
+        uint32_t ncomp = 0;
+        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+            const uint2 rn = runs[i];
+            const uint32_t root = find_root(parent, rn.x);
+            if (root == rn.x)
+                ++ncomp;
+            else
+                __hip_atomic_store(parent + rn.x, root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicAdd(area + root, rn.y);
+        }
+        __threadfence();
+        __syncthreads();
+        // C: the largest component, ties to the smallest first index
+        unsigned long long best = 0ull;
+        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+            const uint32_t s = runs[i].x;
+            if (ld_parent(parent + s) == s) {
+                const uint32_t a = __hip_atomic_load(area + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long key = ((unsigned long long)a << 32) | (0xFFFFFFFFull - s);
+                best = key > best ? key : best;
+            }
+        }
+        best = block_reduce<unsigned long long>(best, s_u64, OpMax());
+        ncomp = block_reduce<uint32_t>(ncomp, s_u32, OpAdd());
+        const uint32_t A = (uint32_t)(best >> 32);
+        const uint32_t kstar = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
+        const bool present = ncomp > 0 && (long long)A >= (long long)J->min_area;
+        // D: sums and box of the selected component
+        unsigned long long sx = 0, sy = 0;
+        uint32_t x0 = 0xFFFFFFFFu, y0 = 0xFFFFFFFFu, x1 = 0, y1 = 0;
+        if (present) {
+            for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+                const uint2 rn = runs[i];
+                if (ld_parent(parent + rn.x) != kstar)
+                    continue;
+                const uint32_t y = rn.x / (uint32_t)W, xs = rn.x - y * (uint32_t)W;
+                const uint32_t xe = xs + rn.y - 1;
+                sx += (unsigned long long)rn.y * xs + (unsigned long long)rn.y * (rn.y - 1) / 2;
+                sy += (unsigned long long)rn.y * y;
+                x0 = min(x0, xs);
+                x1 = max(x1, xe);
+                y0 = min(y0, y);
+                y1 = max(y1, y);
+                if (hand) {
+                    uint64_t *hr = hand + (size_t)y * Wd;
+                    const int wa = (int)(xs >> 6), wb = (int)(xe >> 6);
+                    for (int w = wa; w <= wb; ++w) {
+                        const int lo = (w == wa) ? (int)(xs & 63) : 0;
+                        const int hi = (w == wb) ? (int)(xe & 63) : 63;
+                        const uint64_t m = (hi == 63 ? ~0ull : ((2ull << hi) - 1ull)) & (~0ull << lo);
+                        atomicOr(reinterpret_cast<unsigned long long *>(hr + w), (unsigned long long)m);
+                    }
+                }
+            }
+        }
+        sx = block_reduce<unsigned long long>(sx, s_u64, OpAdd());
+        sy = block_reduce<unsigned long long>(sy, s_u64, OpAdd());
+        x0 = block_reduce<uint32_t>(x0, s_u32, OpMin());
+        y0 = block_reduce<uint32_t>(y0, s_u32, OpMin());
+        x1 = block_reduce<uint32_t>(x1, s_u32, OpMax());
+        y1 = block_reduce<uint32_t>(y1, s_u32, OpMax());
+        if (threadIdx.x == 0) {
+            fizi_pointer o;
+            o.present = present ? 1 : 0;
+            o.click = 0;
+            o.reserved = 0;
+            o.area = 0;
+            o.sum_x = o.sum_y = 0;
+            o.x0 = o.y0 = o.x1 = o.y1 = 0;
+            if (present) {
+                o.area = A;
+                o.sum_x = sx;
+                o.sum_y = sy;
+                o.x0 = x0;
+                o.y0 = y0;
+                o.x1 = x1;
+                o.y1 = y1;
+                const unsigned long long box = (unsigned long long)(x1 - x0 + 1) * (y1 - y0 + 1);
+                o.click = (1000ull * A >= (unsigned long long)J->fill_pm * box) ? 1 : 0;
+            }
+            o.n_components = ncomp;
+            o.inv_gain_q16 = J->inv;
+            o.frame_index = J->frame_index;
+            *J->out = o;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H, int rs, hipStream_t s)
+{
+    const int rows = (H + rs - 1) / rs;
+    const int n = rows * (W / 4);
+    const int grid = min((n + 255) / 256, 4096);
+    k_make_yref<<<grid, 256, 0, s>>>(frame0, yref, W, H, rs);
+    return hipGetLastError();
+}
+
+hipError_t launch_gain(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t, hipStream_t s)
+{
+    if (total_tiles <= 0)
+        return hipSuccess;
+    const int grid = min(total_tiles, n_cu * t.grid_per_cu);
+    k_gain<<<grid, 256, 0, s>>>(const_cast<Table *>(d_tab));
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax(const Table *d_tab, int njobs, uint8_t *bgmin, uint8_t *bgmax, int npx,
+                         int reset, int n_cu, hipStream_t s)
+{
+    const int groups = npx / 4;
+    const int grid = min((groups + 255) / 256, n_cu * 8);
+    k_minmax<<<grid, 256, 0, s>>>(const_cast<Table *>(d_tab), njobs, bgmin, bgmax, npx, reset);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t, hipStream_t s)
+{
+    if (total_tiles <= 0)
+        return hipSuccess;
+    const int grid = min(total_tiles, n_cu * t.grid_per_cu);
+    Table *tab = const_cast<Table *>(d_tab);
+    switch (t.cls_iters) {
+    case 1: k_classify<1><<<grid, 256, 0, s>>>(tab); break;
+    case 2: k_classify<2><<<grid, 256, 0, s>>>(tab); break;
+    case 8: k_classify<8><<<grid, 256, 0, s>>>(tab); break;
+    default: k_classify<4><<<grid, 256, 0, s>>>(tab); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max_ops, int n_cu,
+                        const Tuning &t, hipStream_t s)
+{
+    if (total_tiles <= 0)
+        return hipSuccess;
+    const int rows = t.morph_rows + 2 * max_ops;
+    const int buf_words = rows * max_wd;
+    const size_t lds = 2 * (size_t)buf_words * sizeof(uint64_t);
+    const int grid = min(total_tiles, n_cu * 4);
+    Table *tab = const_cast<Table *>(d_tab);
+    switch (t.morph_rows) {
+    case 8: k_morph<8><<<grid, 256, lds, s>>>(tab, buf_words); break;
+    case 16: k_morph<16><<<grid, 256, lds, s>>>(tab, buf_words); break;
+    case 64: k_morph<64><<<grid, 256, lds, s>>>(tab, buf_words); break;
+    default: k_morph<32><<<grid, 256, lds, s>>>(tab, buf_words); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s)
+{
+    if (njobs <= 0)
+        return hipSuccess;
+    k_resolve<<<njobs, kResolveThreads, 0, s>>>(const_cast<Table *>(d_tab));
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    const size_t grid = std::min<size_t>((n + 255) / 256, 65535);
+    k_fill_u32<<<(unsigned)grid, 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace fizi

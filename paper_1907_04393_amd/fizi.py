@@ -1,0 +1,266 @@
+"""Python binding of libfizi.so: argument marshalling only.
+
+Every step of the pipeline runs in the HIP library; torch supplies device
+memory (the state block, frames, outputs) and the stream. Names follow the C
+ABI in include/fizi.h: learn_background, process_frames, get_pointer.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libfizi.so")
+
+FIZI_OK, FIZI_EINVAL, FIZI_ESTATE, FIZI_ENOMEM, FIZI_EHIP, FIZI_ERANGE = 0, -1, -2, -3, -4, -5
+
+PARAM_FIELDS = ("alpha1_cdeg", "alpha2_cdeg", "gray_S", "bg_delta", "open_iters", "close_iters",
+                "min_area", "click_fill_permille", "gain_row_stride", "gain_lo_q16", "gain_hi_q16")
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in PARAM_FIELDS]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k in PARAM_FIELDS}
+
+
+class PointerC(ctypes.Structure):
+    _fields_ = [("present", ctypes.c_uint8), ("click", ctypes.c_uint8),
+                ("reserved", ctypes.c_uint16), ("area", ctypes.c_uint32),
+                ("sum_x", ctypes.c_uint64), ("sum_y", ctypes.c_uint64),
+                ("x0", ctypes.c_uint32), ("y0", ctypes.c_uint32),
+                ("x1", ctypes.c_uint32), ("y1", ctypes.c_uint32),
+                ("n_components", ctypes.c_uint32), ("inv_gain_q16", ctypes.c_uint32),
+                ("frame_index", ctypes.c_uint64)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("bgmin", ctypes.c_uint64), ("bgmax", ctypes.c_uint64), ("yref", ctypes.c_uint64),
+                ("yref_rows", ctypes.c_uint64), ("total", ctypes.c_uint64)]
+
+
+POINTER_DTYPE = np.dtype([("present", "u1"), ("click", "u1"), ("reserved", "<u2"), ("area", "<u4"),
+                          ("sum_x", "<u8"), ("sum_y", "<u8"), ("x0", "<u4"), ("y0", "<u4"),
+                          ("x1", "<u4"), ("y1", "<u4"), ("n_components", "<u4"),
+                          ("inv_gain_q16", "<u4"), ("frame_index", "<u8")])
+assert POINTER_DTYPE.itemsize == ctypes.sizeof(PointerC) == 56
+
+
+class FiziError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fizi error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, vp, i32, i64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.fizi_last_error.restype = ctypes.c_char_p
+    L.fizi_default_params.argtypes = [P(Params)]
+    L.fizi_validate.argtypes = [P(Geom), P(Params)]
+    L.fizi_state_bytes.argtypes = [P(Geom), P(Params), i32]
+    L.fizi_state_bytes.restype = ctypes.c_size_t
+    L.fizi_state_layout.argtypes = [P(Geom), P(Params), i32, P(Layout)]
+    L.fizi_create.argtypes = [P(Geom), P(Params), i32, vp, ctypes.c_size_t, vp, P(vp)]
+    L.learn_background.argtypes = [vp, vp, i32, i32, vp]
+    L.process_frames.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    L.get_pointer.argtypes = [vp, i64, P(PointerC)]
+    L.fizi_destroy.argtypes = [vp]
+    L.fizi_stage_timing.argtypes = [vp, i32]
+    L.fizi_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
+    _extra_signatures(L)
+    _lib = L
+    return L
+
+
+def _extra_signatures(L):
+    """Signatures of the batched and soft-mask entry points, when present."""
+    P, vp, i32, i64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    if hasattr(L, "fizi_batch_create"):
+        L.fizi_batch_state_bytes.argtypes = [i32, P(Geom), P(Params)]
+        L.fizi_batch_state_bytes.restype = ctypes.c_size_t
+        L.fizi_batch_create.argtypes = [i32, P(Geom), P(Params), vp, ctypes.c_size_t, P(vp)]
+        L.fizi_batch_learn.argtypes = [vp, i32, vp, i32, i32, vp]
+        L.fizi_batch_step.argtypes = [vp, P(vp), P(vp), vp, vp]
+        L.fizi_batch_destroy.argtypes = [vp]
+    if hasattr(L, "fizi_soft_forward"):
+        L.fizi_soft_forward.argtypes = [vp, i64, P(ctypes.c_float), ctypes.c_float, vp, vp]
+        L.fizi_soft_workspace_bytes.argtypes = [i64]
+        L.fizi_soft_workspace_bytes.restype = ctypes.c_size_t
+        L.fizi_soft_backward.argtypes = [vp, vp, i64, P(ctypes.c_float), ctypes.c_float, vp,
+                                         ctypes.c_size_t, vp, vp]
+
+
+def check(rc):
+    if rc != FIZI_OK:
+        raise FiziError(rc, lib().fizi_last_error().decode())
+    return rc
+
+
+def last_error() -> str:
+    return lib().fizi_last_error().decode()
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    check(lib().fizi_default_params(ctypes.byref(p)))
+    for k, v in overrides.items():
+        if k not in PARAM_FIELDS:
+            raise KeyError(k)
+        setattr(p, k, int(v))
+    return p
+
+
+def state_bytes(width, height, params=None, chunk=16) -> int:
+    params = params or default_params()
+    return int(lib().fizi_state_bytes(ctypes.byref(Geom(width, height)), ctypes.byref(params), chunk))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def pointers_to_numpy(t: torch.Tensor) -> np.ndarray:
+    """Device (n, 56) uint8 tensor of fizi_pointer -> structured numpy array."""
+    return t.detach().cpu().numpy().reshape(-1).view(POINTER_DTYPE)
+
+
+def pointer_dict(rec) -> dict:
+    return {k: int(rec[k]) for k in POINTER_DTYPE.names if k != "reserved"}
+
+
+class Context:
+    """One camera stream: its learned model and scratch live in `self.state`."""
+
+    def __init__(self, width, height, params=None, chunk=16, device="cuda", stream=None):
+        L = lib()
+        self.width, self.height = int(width), int(height)
+        self.params = params or default_params()
+        self.chunk = int(chunk)
+        self.geom = Geom(self.width, self.height)
+        nbytes = int(L.fizi_state_bytes(ctypes.byref(self.geom), ctypes.byref(self.params), self.chunk))
+        if nbytes == 0:
+            check(L.fizi_validate(ctypes.byref(self.geom), ctypes.byref(self.params)))
+            raise FiziError(FIZI_EINVAL, "chunk must be in [1, 256]")
+        self.device = torch.device(device)
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        check(L.fizi_create(ctypes.byref(self.geom), ctypes.byref(self.params), self.chunk,
+                            _ptr(self.state), nbytes, _stream(stream), ctypes.byref(self._h)))
+        lay = Layout()
+        check(L.fizi_state_layout(ctypes.byref(self.geom), ctypes.byref(self.params), self.chunk,
+                                  ctypes.byref(lay)))
+        self.layout = lay
+        self.words = self.height * (self.width // 64)
+
+    # -- the C ABI ------------------------------------------------------------
+    def learn_background(self, frames: torch.Tensor, reset=True, stream=None):
+        self._check_frames(frames)
+        check(lib().learn_background(self._h, _ptr(frames), int(frames.shape[0]), int(bool(reset)),
+                                     _stream(stream)))
+
+    def process_frames(self, frames: torch.Tensor, want_fizi=True, want_hand=False, stream=None):
+        """Returns dict(pointers=(n,56) uint8, fizi=(n,H,W/64) int64 bits or
+        None, hand=... or None); all device tensors, filled asynchronously."""
+        self._check_frames(frames)
+        n = int(frames.shape[0])
+        shape = (n, self.height, self.width // 64)
+        fz = torch.empty(shape, dtype=torch.int64, device=self.device) if want_fizi else None
+        hd = torch.empty(shape, dtype=torch.int64, device=self.device) if want_hand else None
+        ptrs = torch.empty((n, 56), dtype=torch.uint8, device=self.device)
+        check(lib().process_frames(self._h, _ptr(frames), n, _ptr(fz), _ptr(hd), _ptr(ptrs),
+                                   _stream(stream)))
+        return dict(pointers=ptrs, fizi=fz, hand=hd)
+
+    def process_into(self, frames, n, fizi=None, hand=None, pointers=None, stream=None):
+        """process_frames into caller tensors (no allocation)."""
+        check(lib().process_frames(self._h, _ptr(frames), int(n), _ptr(fizi), _ptr(hand),
+                                   _ptr(pointers), _stream(stream)))
+
+    def get_pointer(self, frame_index: int) -> dict:
+        out = PointerC()
+        check(lib().get_pointer(self._h, int(frame_index), ctypes.byref(out)))
+        return {k: int(getattr(out, k)) for k, _ in PointerC._fields_ if k != "reserved"}
+
+    STAGES = ("gain", "classify", "morph", "resolve", "learn")
+
+    def stage_timing(self, enable=True):
+        check(lib().fizi_stage_timing(self._h, int(bool(enable))))
+
+    def stage_times(self) -> dict:
+        """{stage: (total ms, launches)} since the last read."""
+        ms = (ctypes.c_double * 5)()
+        n = (ctypes.c_int64 * 5)()
+        check(lib().fizi_stage_times(self._h, ms, n))
+        return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(self.STAGES)}
+
+    # -- helpers --------------------------------------------------------------
+    def model(self):
+        """Views of the learned model inside the state block."""
+        L = self.layout
+        px3 = self.width * self.height * 3
+        bgmin = self.state[L.bgmin:L.bgmin + px3].view(self.height, self.width, 3)
+        bgmax = self.state[L.bgmax:L.bgmax + px3].view(self.height, self.width, 3)
+        ny = int(L.yref_rows) * self.width * 2
+        yref = self.state[L.yref:L.yref + ny].view(torch.int16).view(int(L.yref_rows), self.width)
+        return bgmin, bgmax, yref
+
+    def _check_frames(self, frames):
+        if frames.dtype != torch.uint8 or frames.device != self.device or not frames.is_contiguous():
+            raise FiziError(FIZI_EINVAL, "frames must be a contiguous uint8 tensor on the context's device")
+        if tuple(frames.shape[1:]) != (self.height, self.width, 3):
+            raise FiziError(FIZI_EINVAL, f"frames must be (n, {self.height}, {self.width}, 3)")
+
+    def close(self):
+        if self._h:
+            lib().fizi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def learn_background(ctx: Context, frames, reset=True, stream=None):
+    return ctx.learn_background(frames, reset, stream)
+
+
+def process_frames(ctx: Context, frames, want_fizi=True, want_hand=False, stream=None):
+    return ctx.process_frames(frames, want_fizi, want_hand, stream)
+
+
+def get_pointer(ctx: Context, frame_index: int) -> dict:
+    return ctx.get_pointer(frame_index)
+
+
+def unpack_bits(words: torch.Tensor, width: int) -> np.ndarray:
+    """(..., H, W/64) int64 LSB-first bit rows -> (..., H, W) uint8."""
+    a = words.detach().cpu().numpy().view(np.uint64)
+    b = a.view(np.uint8)   # little-endian: byte k of word j holds pixels 64j + 8k ..
+    bits = np.unpackbits(b, axis=-1, bitorder="little")
+    return bits[..., :width]

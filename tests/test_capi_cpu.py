@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every symbol include/fizi.h declares,
+and its host-only entry points behave (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", txt, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    from paper_1907_04393_amd import fizi
+    L = fizi.lib()
+    names = _declared()
+    assert "learn_background" in names and "process_frames" in names and "get_pointer" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_defaults_match_the_oracle_readings():
+    from oracle import oracle
+    from paper_1907_04393_amd import fizi
+    assert fizi.default_params().as_dict() == oracle.DEFAULTS
+
+
+@pytest.mark.parametrize("bad", [dict(width=100), dict(width=0), dict(height=0), dict(width=8256),
+                                 dict(alpha1_cdeg=36000), dict(gray_S=-1), dict(open_iters=4),
+                                 dict(gain_row_stride=0), dict(gain_lo_q16=70000, gain_hi_q16=60000),
+                                 dict(click_fill_permille=1001)])
+def test_validation_rejects(bad):
+    from paper_1907_04393_amd import fizi
+    L = fizi.lib()
+    g = fizi.Geom(bad.pop("width", 320), bad.pop("height", 240))
+    p = fizi.default_params(**bad)
+    assert L.fizi_validate(ctypes.byref(g), ctypes.byref(p)) == fizi.FIZI_EINVAL
+    assert fizi.last_error()
+    assert L.fizi_state_bytes(ctypes.byref(g), ctypes.byref(p), 4) == 0
+
+
+def test_state_bytes_and_layout():
+    from paper_1907_04393_amd import fizi
+    L = fizi.lib()
+    g = fizi.Geom(1920, 1080)
+    p = fizi.default_params()
+    n1 = L.fizi_state_bytes(ctypes.byref(g), ctypes.byref(p), 1)
+    n8 = L.fizi_state_bytes(ctypes.byref(g), ctypes.byref(p), 8)
+    assert n8 > n1 > 1920 * 1080 * 6
+    lay = fizi.Layout()
+    assert L.fizi_state_layout(ctypes.byref(g), ctypes.byref(p), 8, ctypes.byref(lay)) == 0
+    assert lay.total == n8 and lay.yref_rows == 135
+    assert lay.bgmax >= lay.bgmin + 1920 * 1080 * 3 and lay.bgmin % 256 == 0
+    assert L.fizi_state_bytes(ctypes.byref(g), ctypes.byref(p), 0) == 0
+    assert L.fizi_state_bytes(ctypes.byref(g), ctypes.byref(p), 257) == 0
+
+
+def test_null_arguments_are_errors():
+    from paper_1907_04393_amd import fizi
+    L = fizi.lib()
+    assert L.learn_background(None, None, 1, 1, None) == fizi.FIZI_EINVAL
+    assert L.process_frames(None, None, 1, None, None, None, None) == fizi.FIZI_EINVAL
+    assert L.get_pointer(None, 0, None) == fizi.FIZI_EINVAL
+    assert L.fizi_destroy(None) == 0

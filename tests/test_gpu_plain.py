@@ -1,0 +1,191 @@
+"""GPU parity of the plain path (learn_background, process_frames,
+get_pointer) against the CPU oracle: bit-exact model, I_FIZI, hand mask and
+every pointer field."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import compare, gpu_run, need_gpu, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _small():
+    from paper_1907_04393_amd import scene
+    sc = scene.Scene(scene.small_plain())
+    return sc.bg_frames(0, 30), sc.hand_frames(0, 100)
+
+
+def test_small_scene_full_parity():
+    """320x240, 30 background + 100 hand frames, chunks of 16 (ragged last
+    chunk)."""
+    bg, hand = _small()
+    print("small scene: 320x240, 30 bg + 100 hand", flush=True)
+    g = gpu_run(bg, hand, {}, chunk=16)
+    m, outs = oracle_run(bg, hand, {})
+    compare(g, m, outs, "small")
+    assert sum(o["pointer"]["present"] for o in outs.values()) >= 95
+
+
+def test_incremental_learning_and_get_pointer():
+    from paper_1907_04393_amd import fizi
+    bg, hand = _small()
+    g = gpu_run(bg, hand[:20], {}, chunk=8, learn_split=[7, 7, 16])
+    m, outs = oracle_run(bg, hand[:20], {})
+    compare(g, m, outs, "incremental")
+    ctx = g["ctx"]
+    for k in (0, 7, 19):
+        assert ctx.get_pointer(k) == g["pointers"][k]
+    with pytest.raises(fizi.FiziError) as e:
+        ctx.get_pointer(20)
+    assert e.value.code == fizi.FIZI_ERANGE
+    # indices continue across calls
+    dev = need_gpu()
+    out = ctx.process_frames(hand[20:23].to(dev))
+    torch.cuda.synchronize()
+    ps = fizi.pointers_to_numpy(out["pointers"])
+    assert [int(p["frame_index"]) for p in ps] == [20, 21, 22]
+    assert ctx.get_pointer(21)["frame_index"] == 21
+
+
+def test_process_before_learn_is_an_error():
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    ctx = fizi.Context(64, 8, device=dev, chunk=2)
+    with pytest.raises(fizi.FiziError) as e:
+        ctx.process_frames(torch.zeros((1, 8, 64, 3), dtype=torch.uint8, device=dev))
+    assert e.value.code == fizi.FIZI_ESTATE
+
+
+def _blob_scene(W, H, n_bg, n_hand, seed):
+    """Noisy random background and skin-hued blobs of random size."""
+    g = torch.Generator().manual_seed(seed)
+    base = torch.randint(30, 220, (1, H, W, 3), generator=g).float()
+    bg = (base + torch.randn((n_bg, H, W, 3), generator=g) * 2).round().clamp(0, 255).to(torch.uint8)
+    hand = (base + torch.randn((n_hand, H, W, 3), generator=g) * 2).round().clamp(0, 255)
+    ys = torch.arange(H).view(H, 1)
+    xs = torch.arange(W).view(1, W)
+    for k in range(n_hand):
+        for _ in range(int(torch.randint(0, 5, (1,), generator=g))):
+            cx = int(torch.randint(0, W, (1,), generator=g))
+            cy = int(torch.randint(0, H, (1,), generator=g))
+            a = int(torch.randint(1, max(2, W // 3), (1,), generator=g))
+            b = int(torch.randint(1, max(2, H // 2 + 1), (1,), generator=g))
+            m = ((xs - cx) ** 2 * b * b + (ys - cy) ** 2 * a * a) <= a * a * b * b
+            col = torch.tensor([200.0, 120.0 + 40 * torch.rand(1, generator=g).item(), 80.0])
+            hand[k][m] = col
+        gain = 0.85 + 0.3 * torch.rand(1, generator=g).item()
+        hand[k] = (hand[k] * gain).round().clamp(0, 255)
+    return bg, hand.to(torch.uint8)
+
+
+@pytest.mark.parametrize("W,H", [(64, 1), (64, 2), (128, 37), (192, 100), (640, 33), (256, 257)])
+def test_edge_geometries(W, H):
+    print(f"edge geometry {W}x{H}", flush=True)
+    bg, hand = _blob_scene(W, H, 5, 6, seed=W * 1000 + H)
+    g = gpu_run(bg, hand, {}, chunk=4)
+    m, outs = oracle_run(bg, hand, {})
+    compare(g, m, outs, f"{W}x{H}")
+
+
+PARAM_SETS = [
+    dict(open_iters=0, close_iters=0),
+    dict(open_iters=2, close_iters=1),
+    dict(open_iters=3, close_iters=3),
+    dict(open_iters=0, close_iters=2),
+    dict(bg_delta=0, gray_S=0),
+    dict(alpha1_cdeg=0, alpha2_cdeg=6000),          # narrow, no wrap
+    dict(alpha1_cdeg=1000, alpha2_cdeg=1000),       # one hue
+    dict(alpha1_cdeg=30000, alpha2_cdeg=12000),     # exactly a half turn
+    dict(alpha1_cdeg=20000, alpha2_cdeg=15000),     # wide, wrapping
+    dict(gain_row_stride=1, min_area=50, click_fill_permille=500),
+    dict(gain_row_stride=64, gain_lo_q16=65536, gain_hi_q16=65536),
+]
+
+
+@pytest.mark.parametrize("k", range(len(PARAM_SETS)))
+def test_parameter_readings(k):
+    params = PARAM_SETS[k]
+    print("params", params, flush=True)
+    bg, hand = _blob_scene(192, 70, 6, 5, seed=77 + k)
+    g = gpu_run(bg, hand, params, chunk=3)
+    m, outs = oracle_run(bg, hand, params)
+    compare(g, m, outs, str(params))
+
+
+def test_degenerate_frames():
+    """Frames identical to the background; an all-skin frame; a one-pixel
+    checkerboard of skin (the most runs a row can have)."""
+    W, H = 128, 48
+    bgc = torch.full((2, H, W, 3), 40, dtype=torch.uint8)
+    bgc[..., 2] = 90                                  # bluish, not skin
+    skin = torch.tensor([210, 140, 90], dtype=torch.uint8)
+    full = skin.view(1, 1, 1, 3).expand(1, H, W, 3).clone()
+    chk = bgc[:1].clone()
+    yy, xx = torch.meshgrid(torch.arange(H), torch.arange(W), indexing="ij")
+    chk[0][((yy + xx) % 2) == 0] = skin
+    stripes = bgc[:1].clone()
+    stripes[0][:, ::2] = skin
+    hand = torch.cat([bgc[:1], full, chk, stripes])
+    for params in ({}, dict(open_iters=0, close_iters=0), dict(gain_lo_q16=65536, gain_hi_q16=65536)):
+        print("degenerate", params, flush=True)
+        g = gpu_run(bgc, hand, params, chunk=4)
+        m, outs = oracle_run(bgc, hand, params)
+        compare(g, m, outs, f"degenerate {params}")
+    assert outs[0]["pointer"]["present"] == 0
+
+
+def test_hue_gray_all_2e24_colours():
+    """Every RGB triple once (a 4096x4096 frame), gain pinned to 1, a
+    background point-box that every colour leaves, no morphology: I_FIZI is
+    then exactly I_R2 AND I_R3, compared with the oracle for all 2^24
+    colours and several hue intervals."""
+    from oracle import oracle
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    i = np.arange(1 << 24, dtype=np.uint32)
+    frame = np.stack([(i >> 16) & 255, (i >> 8) & 255, i & 255], axis=1).astype(np.uint8)
+    frame = frame.reshape(1, 4096, 4096, 3)
+    bgf = ((frame.astype(np.int32) + 128) % 256).astype(np.uint8)
+    fd = torch.from_numpy(frame).to(dev)
+    bd = torch.from_numpy(bgf).to(dev)
+    for (a1, a2, S) in [(33000, 7500, 20), (0, 6000, 0), (1000, 1000, 1), (30000, 12000, 5),
+                        (20000, 15000, 20)]:
+        print("2^24 sweep", a1, a2, S, flush=True)
+        params = dict(alpha1_cdeg=a1, alpha2_cdeg=a2, gray_S=S, bg_delta=0, open_iters=0,
+                      close_iters=0, gain_lo_q16=65536, gain_hi_q16=65536)
+        ctx = fizi.Context(4096, 4096, fizi.default_params(**params), chunk=1, device=dev)
+        ctx.learn_background(bd)
+        out = ctx.process_frames(fd, want_fizi=True)
+        torch.cuda.synchronize()
+        got = fizi.unpack_bits(out["fizi"], 4096)[0].reshape(-1)
+        ref = oracle.masks(frame[0], bgf[0], bgf[0], oracle.params(**params))
+        assert ref["r1"].all()
+        want = ref["raw"].reshape(-1)
+        if not np.array_equal(got, want):
+            bad = np.nonzero(got != want)[0][:5]
+            raise AssertionError(f"({a1},{a2},{S}) differs at colours {[hex(int(b)) for b in bad]}")
+        ctx.close()
+        del out
+
+
+def test_hd_scene_parity():
+    """1920x1080, sigma 5, two distractors, 50 background frames, 32 hand
+    frames in chunks of 16."""
+    from paper_1907_04393_amd import scene
+    sc = scene.Scene(scene.hd_plain())
+    bg = sc.bg_frames(0, 50)
+    hand = sc.hand_frames(0, 32)
+    print("hd scene 1920x1080", flush=True)
+    g = gpu_run(bg, hand, {}, chunk=16)
+    m, outs = oracle_run(bg, hand, {})
+    compare(g, m, outs, "hd")
+    assert all(o["pointer"]["present"] for o in outs.values())
+
+
+def test_determinism():
+    bg, hand = _small()
+    a = gpu_run(bg, hand[:16], {}, chunk=16)
+    b = gpu_run(bg, hand[:16], {}, chunk=5)
+    assert a["pointers"] == b["pointers"]
+    assert np.array_equal(a["fizi"], b["fizi"]) and np.array_equal(a["hand"], b["hand"])
