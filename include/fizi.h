@@ -184,6 +184,96 @@ int fizi_stage_timing(fizi_ctx *ctx, int32_t enable);
 int fizi_stage_times(fizi_ctx *ctx, double *h_ms /* [FIZI_NSTAGES] */,
                      int64_t *h_launches /* [FIZI_NSTAGES] */);
 
+/* ---- Batched form ---------------------------------------------------------
+ * Many camera streams (each its own geometry, thresholds and background
+ * model) go through one pipeline pass per frame step: the same per-frame
+ * method as process_frames, with the frames of all active streams in one set
+ * of launches (or one persistent kernel), optionally replayed from a
+ * hipGraph. Streams are independent given their models (Section 2: the
+ * running phase treats each camera image on its own). */
+typedef struct fizi_batch fizi_batch;
+
+enum {
+    FIZI_BATCH_DIRECT = 0,            /* four kernels per step, launched directly */
+    FIZI_BATCH_GRAPH = 1,             /* the same, replayed from a hipGraph */
+    FIZI_BATCH_PERSISTENT = 2,        /* one persistent fused kernel per step */
+    FIZI_BATCH_PERSISTENT_GRAPH = 3   /* the persistent kernel from a hipGraph */
+};
+
+/* Device bytes for n_streams (1..256) streams; geoms and params are arrays of
+ * n_streams. 0 when an argument is invalid. */
+size_t fizi_batch_state_bytes(int32_t n_streams, const fizi_geom *geoms, const fizi_params *params);
+
+/* Creates a batch over the caller's 256-byte aligned device block. */
+int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_params *params,
+                      void *d_state, size_t state_bytes, fizi_batch **out);
+
+/* learn_background for one stream of the batch. Async. */
+int fizi_batch_learn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, int32_t n_frames,
+                     int32_t reset, void *stream);
+
+/* One frame step. h_frames: host array of n_streams device frame pointers,
+ * NULL for a stream with no frame this step. h_fizi_bits: NULL, or a host
+ * array of n_streams device bit-mask pointers (entries may be NULL).
+ * d_pointers: device array of n_streams pointers; entry i is written when
+ * stream i has a frame. FIZI_ESTATE if an active stream has no model. Async. */
+int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *const *h_fizi_bits,
+                    fizi_pointer *d_pointers, void *stream);
+
+/* Selects how steps are launched (FIZI_BATCH_*); waits for pending steps. */
+int fizi_batch_set_mode(fizi_batch *b, int32_t mode);
+
+/* Waits for all steps and returns (and clears) the error word: non-zero when
+ * a persistent step gave up waiting at a grid barrier (its outputs are then
+ * not valid). */
+int fizi_batch_status(fizi_batch *b, uint32_t *h_flags);
+
+/* Offsets of stream stream_id's model inside the batch state block
+ * (`total` is 0). */
+int fizi_batch_state_layout(fizi_batch *b, int32_t stream_id, fizi_layout *out);
+
+/* Measurement hook of the batch (see fizi_stage_timing); in the persistent
+ * modes the fused kernel is reported as stage 1. */
+int fizi_batch_stage_timing(fizi_batch *b, int32_t enable);
+int fizi_batch_stage_times(fizi_batch *b, double *h_ms, int64_t *h_launches);
+
+/* Waits for the batch's work and releases its host resources. */
+int fizi_batch_destroy(fizi_batch *b);
+
+/* ---- Differentiable form (calibration) -------------------------------------
+ * A soft, sigmoid-relaxed skin mask and its hand-written adjoint, used to
+ * calibrate a chroma skin model from ground-truth masks. Not in the paper,
+ * whose skin test is the hard hue interval of Section 3.1 (iii); the hard
+ * path above is unchanged by it. For each RGB pixel (uint8, interleaved):
+ *   Cb = 128 - 0.168736 R - 0.331264 G + 0.5 B,
+ *   Cr = 128 + 0.5 R - 0.418688 G - 0.081312 B       (BT.601 full range),
+ *   d  = sqrt(delta^T S^-1 delta), delta = (Cb - mu_b, Cr - mu_r),
+ *   m  = sigmoid((theta - d) / T),
+ * with params6 = {mu_b, mu_r, s_bb, s_br, s_rr, theta} (host floats; S =
+ * [[s_bb, s_br], [s_br, s_rr]] must be positive definite) and T > 0. The
+ * per-pixel arithmetic is FP32; sums are FP64 in a fixed order, so results
+ * are bitwise reproducible. Where d = 0 the distance contributes no
+ * gradient. d_frames is 4-byte aligned, npx >= 1 pixels. */
+
+/* m for npx pixels into d_mask (FP32, 16-byte aligned). Async. */
+int fizi_soft_forward(const uint8_t *d_frames, int64_t npx, const float params6[6], float T,
+                      float *d_mask, void *stream);
+
+/* Device workspace bytes the two calls below need (caller-owned). */
+size_t fizi_soft_workspace_bytes(int64_t npx);
+
+/* Given dL/dm per pixel (FP32), writes dL/dparams6 to d_grad6 (6 doubles,
+ * device). Async. */
+int fizi_soft_backward(const uint8_t *d_frames, const float *d_dLdm, int64_t npx,
+                       const float params6[6], float T, void *d_workspace, size_t workspace_bytes,
+                       double *d_grad6, void *stream);
+
+/* Fused loss and gradient against a ground-truth mask d_gt (uint8 0/1 per
+ * pixel): L = mean binary cross-entropy of m; d_out7 receives the 6
+ * gradients of L followed by L (7 doubles, device). Async. */
+int fizi_soft_bce(const uint8_t *d_frames, const uint8_t *d_gt, int64_t npx, const float params6[6],
+                  float T, void *d_workspace, size_t workspace_bytes, double *d_out7, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *fizi_last_error(void);
 

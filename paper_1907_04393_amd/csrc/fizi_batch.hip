@@ -1,0 +1,333 @@
+// C ABI of the batched form: many camera streams of uneven resolution, one
+// pipeline pass over all of them per frame step (include/fizi.h).
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fizi_host.h"
+
+using namespace fizi;
+
+struct fizi_batch {
+    int n = 0;
+    std::vector<Model> m;
+    std::vector<Slot> slot;
+    std::vector<uint64_t> frames;      // frames stepped per stream
+    Tuning tune{};
+    int max_wd = 0, max_ops = 0;
+    uint8_t *d = nullptr;
+    int device = 0, n_cu = 0;
+    TableRing ring;
+    StageClock clk;
+    int mode = FIZI_BATCH_DIRECT;
+    hipStream_t cap = nullptr;                 // capture stream for graphs
+    hipGraphExec_t graph[kTabSlots] = {};
+    uint8_t *persist = nullptr;                // fused-kernel barrier state
+    hipEvent_t order_ev = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool have_last = false;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t tables, persist;
+    std::vector<size_t> model, slot;
+    size_t total;
+};
+
+int check_streams(int32_t n, const fizi_geom *geoms, const fizi_params *params)
+{
+    if (n < 1 || n > kMaxJobs)
+        return fail(FIZI_EINVAL, "n_streams must be in [1, 256]");
+    if (!geoms || !params)
+        return fail(FIZI_EINVAL, "null geometry or parameter array");
+    for (int i = 0; i < n; ++i)
+        FIZI_TRY(validate(&geoms[i], &params[i]));
+    return FIZI_OK;
+}
+
+BatchLayout batch_layout(int32_t n, const fizi_geom *geoms, const fizi_params *params)
+{
+    BatchLayout L;
+    size_t off = 0;
+    L.tables = off;
+    off += TableRing::device_bytes();
+    L.persist = off;
+    off += align256(persist_state_bytes());
+    L.model.resize(n);
+    L.slot.resize(n);
+    for (int i = 0; i < n; ++i) {
+        L.model[i] = off;
+        off += align256(model_bytes(geoms[i], params[i]));
+        L.slot[i] = off;
+        off += align256(slot_bytes(geoms[i]));
+    }
+    L.total = align256(off);
+    return L;
+}
+
+int order_after_previous(fizi_batch *b, hipStream_t s)
+{
+    if (b->have_last && b->last_stream != s)
+        FIZI_HIP(hipStreamWaitEvent(s, b->order_ev, 0));
+    return FIZI_OK;
+}
+
+int mark_last(fizi_batch *b, hipStream_t s)
+{
+    FIZI_HIP(hipEventRecord(b->order_ev, s));
+    b->last_stream = s;
+    b->have_last = true;
+    return FIZI_OK;
+}
+
+// Enqueues the table upload and the pipeline of one step on s (direct or
+// persistent mode) with launch shapes that do not depend on the active set.
+int enqueue_step(fizi_batch *b, int slot, int njobs, bool fixed, hipStream_t s, StageClock *clk)
+{
+    const Table &T = *b->ring.h[slot];
+    FIZI_HIP(hipMemcpyAsync(b->ring.d[slot], &T, table_bytes(fixed ? b->n : njobs),
+                            hipMemcpyHostToDevice, s));
+    if (b->mode == FIZI_BATCH_PERSISTENT) {
+        FIZI_HIP(launch_persistent(b->ring.d[slot], b->max_wd, b->max_ops, b->n_cu, b->tune, b->persist, s,
+                                   clk ? clk->next(FIZI_STAGE_CLASSIFY) : StageEvents{}));
+        return FIZI_OK;
+    }
+    return run_pipeline(b->ring.d[slot], T, njobs, b->n, b->max_wd, b->max_ops, b->tune, b->n_cu, fixed, s,
+                        clk);
+}
+
+// Graph of one table slot: upload + pipeline, captured once.
+int graph_for(fizi_batch *b, int slot)
+{
+    if (b->graph[slot])
+        return FIZI_OK;
+    if (!b->cap)
+        FIZI_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    FIZI_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+    const int rc = enqueue_step(b, slot, b->n, true, b->cap, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc != FIZI_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return rc;
+    }
+    FIZI_HIP(e);
+    const hipError_t e2 = hipGraphInstantiate(&b->graph[slot], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    FIZI_HIP(e2);
+    return FIZI_OK;
+}
+
+void drop_graphs(fizi_batch *b)
+{
+    for (int i = 0; i < kTabSlots; ++i)
+        if (b->graph[i]) {
+            (void)hipGraphExecDestroy(b->graph[i]);
+            b->graph[i] = nullptr;
+        }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fizi_batch_state_bytes(int32_t n_streams, const fizi_geom *geoms, const fizi_params *params)
+{
+    if (check_streams(n_streams, geoms, params) != FIZI_OK)
+        return 0;
+    return batch_layout(n_streams, geoms, params).total;
+}
+
+int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_params *params, void *d_state,
+                      size_t state_bytes, fizi_batch **out)
+{
+    FIZI_TRY(check_streams(n_streams, geoms, params));
+    if (!d_state || !out)
+        return fail(FIZI_EINVAL, "null d_state or out");
+    if (reinterpret_cast<uintptr_t>(d_state) % 256 != 0)
+        return fail(FIZI_EINVAL, "d_state must be 256-byte aligned");
+    const BatchLayout L = batch_layout(n_streams, geoms, params);
+    if (state_bytes < L.total)
+        return fail(FIZI_ENOMEM, "state block smaller than fizi_batch_state_bytes()");
+    fizi_batch *b = new (std::nothrow) fizi_batch();
+    if (!b)
+        return fail(FIZI_ENOMEM, "host allocation failed");
+    b->n = n_streams;
+    b->d = static_cast<uint8_t *>(d_state);
+    b->m.resize(n_streams);
+    b->slot.resize(n_streams);
+    b->frames.assign(n_streams, 0);
+    int max_w = 0;
+    for (int i = 0; i < n_streams; ++i) {
+        model_at(b->m[i], geoms[i], params[i], b->d + L.model[i]);
+        b->slot[i] = slot_at(geoms[i], b->d + L.slot[i]);
+        max_w = std::max(max_w, geoms[i].width);
+        b->max_ops = std::max(b->max_ops, morph_ops(params[i]));
+    }
+    b->max_wd = max_w / 64;
+    b->tune = tuning_for(max_w, b->max_ops);
+    b->persist = b->d + L.persist;
+    int rc = device_cu_count(&b->device, &b->n_cu);
+    if (rc == FIZI_OK)
+        rc = b->ring.init(b->d + L.tables);
+    if (rc == FIZI_OK) {
+        hipError_t e = hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = (hipError_t)launch_fill_u32(reinterpret_cast<uint32_t *>(b->persist), 0u,
+                                             persist_state_bytes() / 4, nullptr);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess)
+            rc = fail(FIZI_EHIP, std::string("fizi_batch_create: ") + hipGetErrorString(e));
+    }
+    if (rc != FIZI_OK) {
+        const std::string msg = fizi_last_error();
+        fizi_batch_destroy(b);
+        return fail(rc, msg);
+    }
+    *out = b;
+    return FIZI_OK;
+}
+
+int fizi_batch_learn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, int32_t n_frames, int32_t reset,
+                     void *stream)
+{
+    if (!b || !d_frames)
+        return fail(FIZI_EINVAL, "null batch or frames");
+    if (stream_id < 0 || stream_id >= b->n)
+        return fail(FIZI_EINVAL, "stream_id out of range");
+    if (n_frames < 1)
+        return fail(FIZI_EINVAL, "n_frames must be >= 1");
+    Model &m = b->m[stream_id];
+    if (!reset && !m.learned)
+        return fail(FIZI_ESTATE, "learning without reset needs a learned model");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FIZI_TRY(order_after_previous(b, s));
+    FIZI_TRY(learn_model(m, b->ring, b->tune, b->n_cu, d_frames, n_frames, reset, s, &b->clk));
+    return mark_last(b, s);
+}
+
+int fizi_batch_set_mode(fizi_batch *b, int32_t mode)
+{
+    if (!b)
+        return fail(FIZI_EINVAL, "null batch");
+    if (mode < FIZI_BATCH_DIRECT || mode > FIZI_BATCH_PERSISTENT_GRAPH)
+        return fail(FIZI_EINVAL, "unknown batch mode");
+    if (b->have_last)
+        FIZI_HIP(hipEventSynchronize(b->order_ev));
+    const bool persistent = mode == FIZI_BATCH_PERSISTENT || mode == FIZI_BATCH_PERSISTENT_GRAPH;
+    const bool old_persistent = b->mode == FIZI_BATCH_PERSISTENT || b->mode == FIZI_BATCH_PERSISTENT_GRAPH;
+    if (persistent != old_persistent)
+        drop_graphs(b);
+    b->mode = mode;
+    return FIZI_OK;
+}
+
+int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *const *h_fizi_bits,
+                    fizi_pointer *d_pointers, void *stream)
+{
+    if (!b || !h_frames || !d_pointers)
+        return fail(FIZI_EINVAL, "null batch, frame array or pointer array");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < b->n; ++i)
+        if (h_frames[i] && !b->m[i].learned)
+            return fail(FIZI_ESTATE, "a stream in the step has no learned background");
+    FIZI_TRY(order_after_previous(b, s));
+    int slot;
+    FIZI_TRY(b->ring.take(&slot));
+    Table &T = *b->ring.h[slot];
+    int k = 0;
+    for (int i = 0; i < b->n; ++i) {
+        if (!h_frames[i])
+            continue;
+        Job &J = T.jobs[k++];
+        fill_job(b->m[i], b->tune.morph_rows, J);
+        set_scratch(J, b->slot[i]);
+        J.frame = h_frames[i];
+        if (h_fizi_bits && h_fizi_bits[i])
+            J.fizi = h_fizi_bits[i];
+        J.out = d_pointers + i;
+        J.frame_index = b->frames[i]++;
+    }
+    set_prefixes(T, k, b->tune);
+    const bool graphed = b->mode == FIZI_BATCH_GRAPH || b->mode == FIZI_BATCH_PERSISTENT_GRAPH;
+    if (k > 0) {
+        if (graphed) {
+            const int saved = b->mode;
+            b->mode = saved == FIZI_BATCH_GRAPH ? FIZI_BATCH_DIRECT : FIZI_BATCH_PERSISTENT;
+            const int rc = graph_for(b, slot);
+            b->mode = saved;
+            FIZI_TRY(rc);
+            FIZI_HIP(hipGraphLaunch(b->graph[slot], s));
+        } else {
+            FIZI_TRY(enqueue_step(b, slot, k, false, s, &b->clk));
+        }
+    }
+    FIZI_TRY(b->ring.finish(slot, s));
+    return mark_last(b, s);
+}
+
+int fizi_batch_status(fizi_batch *b, uint32_t *h_flags)
+{
+    if (!b || !h_flags)
+        return fail(FIZI_EINVAL, "null argument");
+    if (b->have_last)
+        FIZI_HIP(hipEventSynchronize(b->order_ev));
+    uint32_t *err = &reinterpret_cast<PersistState *>(b->persist)->error;
+    FIZI_HIP(hipMemcpy(h_flags, err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (*h_flags) {
+        FIZI_HIP(launch_fill_u32(err, 0u, 1, nullptr));
+        FIZI_HIP(hipStreamSynchronize(nullptr));
+    }
+    return FIZI_OK;
+}
+
+int fizi_batch_stage_timing(fizi_batch *b, int32_t enable)
+{
+    if (!b)
+        return fail(FIZI_EINVAL, "null batch");
+    return b->clk.enable(enable != 0);
+}
+
+int fizi_batch_stage_times(fizi_batch *b, double *h_ms, int64_t *h_launches)
+{
+    if (!b || !h_ms || !h_launches)
+        return fail(FIZI_EINVAL, "null argument");
+    return b->clk.read(h_ms, h_launches);
+}
+
+int fizi_batch_state_layout(fizi_batch *b, int32_t stream_id, fizi_layout *out)
+{
+    if (!b || !out || stream_id < 0 || stream_id >= b->n)
+        return fail(FIZI_EINVAL, "bad batch, stream or output");
+    const Model &m = b->m[stream_id];
+    out->bgmin = (uint64_t)(m.bgmin - b->d);
+    out->bgmax = (uint64_t)(m.bgmax - b->d);
+    out->yref = (uint64_t)(reinterpret_cast<uint8_t *>(m.yref) - b->d);
+    out->yref_rows = (uint64_t)m.yref_rows;
+    out->total = 0;
+    return FIZI_OK;
+}
+
+int fizi_batch_destroy(fizi_batch *b)
+{
+    if (!b)
+        return FIZI_OK;
+    if (b->have_last)
+        (void)hipEventSynchronize(b->order_ev);
+    drop_graphs(b);
+    if (b->cap)
+        (void)hipStreamDestroy(b->cap);
+    b->ring.destroy();
+    b->clk.destroy();
+    if (b->order_ev)
+        (void)hipEventDestroy(b->order_ev);
+    delete b;
+    return FIZI_OK;
+}
+
+}  // extern "C"

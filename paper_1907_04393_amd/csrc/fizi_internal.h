@@ -58,11 +58,12 @@ struct Job {
     uint64_t frame_index;
     int32_t W, H, Wd, rs;
     uint32_t run_cap;
+    int32_t band;              // morphology band height (rows)
     int32_t delta, S1, open_it, close_it, min_area, fill_pm, glo, ghi;
     HueTest hue;
     // accumulators (zero when the table is uploaded)
-    unsigned long long num, den;
-    uint32_t done, inv, nruns, flags;
+    unsigned long long num, den;   // gain sums over usable sampled pixels
+    uint32_t nruns, flags;
 };
 
 struct TableHeader {
@@ -90,18 +91,36 @@ struct Tuning {
 
 inline int cls_tile_px(const Tuning &t) { return 1024 * t.cls_iters; }
 
+// Counters of the persistent fused step's grid barriers (device memory,
+// zero between launches).
+struct PersistState {
+    unsigned int arrived;    // barrier arrivals in the current launch
+    unsigned int finished;   // blocks done with the current launch
+    unsigned int error;      // a barrier wait gave up (sticky until read)
+    unsigned int pad[61];
+};
+inline size_t persist_state_bytes() { return sizeof(PersistState); }
+
+// Optional start/stop events taken from a kernel's own dispatch (measurement).
+struct StageEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+
 // Kernel launchers (fizi_kernels.hip). Each returns the hipError_t of its launch.
 hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H, int rs,
                             hipStream_t s);
 hipError_t launch_gain(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t,
-                       hipStream_t s);
+                       hipStream_t s, StageEvents ev = {});
 hipError_t launch_minmax(const Table *d_tab, int njobs, uint8_t *bgmin, uint8_t *bgmax,
-                         int npx, int reset, int n_cu, hipStream_t s);
+                         int npx, int reset, int n_cu, hipStream_t s, StageEvents ev = {});
 hipError_t launch_classify(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t,
-                           hipStream_t s);
+                           hipStream_t s, StageEvents ev = {});
 hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max_ops, int n_cu,
-                        const Tuning &t, hipStream_t s);
-hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s);
+                        const Tuning &t, hipStream_t s, StageEvents ev = {});
+hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev = {});
+hipError_t launch_persistent(const Table *d_tab, int max_wd, int max_ops, int n_cu, const Tuning &t,
+                             uint8_t *persist, hipStream_t s, StageEvents ev = {});
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 
 }  // namespace fizi

@@ -15,12 +15,48 @@
 //                (Section 3.1, last paragraph)
 //   k_resolve    8-connected components by union-find over runs, hand-zone
 //                selection and the pointer (Section 2, Mouse module)
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+
 #include "fizi_internal.h"
 
 namespace fizi {
 namespace {
 
 constexpr int kWave = 64;
+
+#define GLOBAL __attribute__((address_space(1)))
+
+// Pointers in the job table are generic; casting them to the global address
+// space lets the compiler emit global_* instead of flat_* accesses.
+template <typename T>
+__device__ __forceinline__ GLOBAL T *G(T *p)
+{
+    return (GLOBAL T *)p;
+}
+
+// A frame's union-find forest is only touched by one workgroup per kernel,
+// so its atomics are workgroup-scoped (performed in the XCD's L2, no fences).
+__device__ __forceinline__ uint32_t ld_wg(GLOBAL uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void st_wg(GLOBAL uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Accumulators that other workgroups update with atomics (the gain sums, the
+// run count) are read with device-scope atomic loads, which bypass the
+// scalar cache; in the persistent step they are written earlier in the same
+// launch.
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ int find_job(const int32_t *pre, int nj, int t)
 {
@@ -41,6 +77,21 @@ __device__ __forceinline__ uint32_t corr(uint32_t v, uint32_t inv)
 {
     uint32_t t = (v * inv + 32768u) >> 16;
     return t < 255u ? t : 255u;
+}
+
+// Q16 inverse gain from the sums of reference and frame luminance: rounded
+// half up and clamped; 1.0 when no sampled pixel was usable.
+__device__ __forceinline__ uint32_t inv_gain(unsigned long long num, unsigned long long den,
+                                             int glo, int ghi)
+{
+    if (den == 0)
+        return 65536u;
+    unsigned long long q = (num * 65536ull + den / 2) / den;
+    if (q < (unsigned long long)glo)
+        q = (unsigned long long)glo;
+    if (q > (unsigned long long)ghi)
+        q = (unsigned long long)ghi;
+    return (uint32_t)q;
 }
 
 // Skin-hue membership without division; see HueTest. Chroma > 0 is checked
@@ -112,76 +163,66 @@ __global__ __launch_bounds__(256) void k_make_yref(const uint8_t *__restrict__ f
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gain(Table *__restrict__ T)
+// One sampled row of one frame: sums of reference and frame luminance over
+// its usable pixels, added to the frame's accumulators.
+__device__ __forceinline__ void gain_tile(Table *__restrict__ T, int nj, int t)
 {
     __shared__ uint32_t s_num[256 / kWave], s_den[256 / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int j = find_job(T->h.gain_pre, nj, t);
+    Job *J = &T->jobs[j];
+    const int rr = t - T->h.gain_pre[j];
+    const int W = J->W;
+    const GLOBAL uint32_t *row = G(reinterpret_cast<const uint32_t *>(J->frame + (size_t)rr * J->rs * W * 3));
+    const GLOBAL uint64_t *yr = G(reinterpret_cast<const uint64_t *>(J->yref + (size_t)rr * W));
+    const HueTest h = J->hue;
+    uint32_t num = 0, den = 0;
+    for (int g = threadIdx.x; g < W / 4; g += blockDim.x) {
+        const uint32_t w0 = row[3 * g], w1 = row[3 * g + 1], w2 = row[3 * g + 2];
+        const uint64_t yv = yr[g];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = byte_of(w0, w1, w2, 3 * k), gg = byte_of(w0, w1, w2, 3 * k + 1),
+                           b = byte_of(w0, w1, w2, 3 * k + 2);
+            const uint32_t y = (uint32_t)(yv >> (16 * k)) & 0xFFFFu;
+            bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
+            if (ok) {
+                const int mx = max(max((int)r, (int)gg), (int)b);
+                const int mn = min(min((int)r, (int)gg), (int)b);
+                if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
+                    ok = false;
+            }
+            if (ok) {
+                num += y;
+                den += r + 2 * gg + b;
+            }
+        }
+    }
+    num = wave_sum(num);
+    den = wave_sum(den);
+    if (lane == 0) {
+        s_num[wave] = num;
+        s_den[wave] = den;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long n = 0, d = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+            n += s_num[w];
+            d += s_den[w];
+        }
+        atomicAdd(&J->num, n);
+        atomicAdd(&J->den, d);
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_gain(Table *__restrict__ T)
+{
     const int nj = T->h.njobs;
     const int total = T->h.gain_pre[nj];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const int j = find_job(T->h.gain_pre, nj, t);
-        Job *J = &T->jobs[j];
-        const int rr = t - T->h.gain_pre[j];
-        const int W = J->W;
-        const uint32_t *row = reinterpret_cast<const uint32_t *>(J->frame + (size_t)rr * J->rs * W * 3);
-        const uint2 *yr = reinterpret_cast<const uint2 *>(J->yref + (size_t)rr * W);
-        const HueTest h = J->hue;
-        uint32_t num = 0, den = 0;
-        for (int g = threadIdx.x; g < W / 4; g += blockDim.x) {
-            const uint32_t w0 = row[3 * g], w1 = row[3 * g + 1], w2 = row[3 * g + 2];
-            const uint2 yv = yr[g];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t r = byte_of(w0, w1, w2, 3 * k), gg = byte_of(w0, w1, w2, 3 * k + 1),
-                               b = byte_of(w0, w1, w2, 3 * k + 2);
-                const uint32_t y = ((k < 2 ? yv.x : yv.y) >> (16 * (k & 1))) & 0xFFFFu;
-                bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
-                if (ok) {
-                    const int mx = max(max((int)r, (int)gg), (int)b);
-                    const int mn = min(min((int)r, (int)gg), (int)b);
-                    if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
-                        ok = false;
-                }
-                if (ok) {
-                    num += y;
-                    den += r + 2 * gg + b;
-                }
-            }
-        }
-        num = wave_sum(num);
-        den = wave_sum(den);
-        if (lane == 0) {
-            s_num[wave] = num;
-            s_den[wave] = den;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long n = 0, d = 0;
-            for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
-                n += s_num[w];
-                d += s_den[w];
-            }
-            atomicAdd(&J->num, n);
-            atomicAdd(&J->den, d);
-            __threadfence();
-            const uint32_t tiles = (uint32_t)(T->h.gain_pre[j + 1] - T->h.gain_pre[j]);
-            const uint32_t prev = atomicAdd(&J->done, 1u);
-            if (prev == tiles - 1) {
-                __threadfence();
-                const unsigned long long N = __hip_atomic_load(&J->num, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long D = __hip_atomic_load(&J->den, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                uint32_t inv = 65536u;
-                if (D != 0) {
-                    unsigned long long q = (N * 65536ull + D / 2) / D;
-                    if (q < (unsigned long long)J->glo) q = (unsigned long long)J->glo;
-                    if (q > (unsigned long long)J->ghi) q = (unsigned long long)J->ghi;
-                    inv = (uint32_t)q;
-                }
-                __hip_atomic_store(&J->inv, inv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        __syncthreads();
-    }
+    for (int t = blockIdx.x; t < total; t += gridDim.x)
+        gain_tile(T, nj, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,10 +230,14 @@ __global__ __launch_bounds__(256) void k_minmax(Table *__restrict__ T, int nj,
                                                 uint8_t *__restrict__ bgmin,
                                                 uint8_t *__restrict__ bgmax, int npx, int reset)
 {
+    __shared__ uint32_t s_inv[kMaxJobs];
+    for (int j = threadIdx.x; j < nj; j += blockDim.x)
+        s_inv[j] = inv_gain(T->jobs[j].num, T->jobs[j].den, T->jobs[j].glo, T->jobs[j].ghi);
+    __syncthreads();
     const int ngroups = npx / 4;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += gridDim.x * blockDim.x) {
-        uint32_t *pmin = reinterpret_cast<uint32_t *>(bgmin) + 3 * g;
-        uint32_t *pmax = reinterpret_cast<uint32_t *>(bgmax) + 3 * g;
+        GLOBAL uint32_t *pmin = G(reinterpret_cast<uint32_t *>(bgmin)) + 3 * g;
+        GLOBAL uint32_t *pmax = G(reinterpret_cast<uint32_t *>(bgmax)) + 3 * g;
         uint32_t lo[12], hi[12];
         if (reset) {
 #pragma unroll
@@ -210,8 +255,8 @@ __global__ __launch_bounds__(256) void k_minmax(Table *__restrict__ T, int nj,
             }
         }
         for (int j = 0; j < nj; ++j) {
-            const uint32_t *f = reinterpret_cast<const uint32_t *>(T->jobs[j].frame) + 3 * g;
-            const uint32_t inv = T->jobs[j].inv;
+            const GLOBAL uint32_t *f = G(reinterpret_cast<const uint32_t *>(T->jobs[j].frame)) + 3 * g;
+            const uint32_t inv = s_inv[j];
             const uint32_t w0 = f[0], w1 = f[1], w2 = f[2];
 #pragma unroll
             for (int i = 0; i < 12; ++i) {
@@ -241,68 +286,73 @@ __global__ __launch_bounds__(256) void k_minmax(Table *__restrict__ T, int nj,
 // tests only run for pixels already outside the background box, so waves of
 // pure background skip them.
 template <int ITERS>
+__device__ __forceinline__ void classify_tile(Table *__restrict__ T, int nj, int t)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int j = find_job(T->h.cls_pre, nj, t);
+    const Job *J = &T->jobs[j];
+    const int tile = t - T->h.cls_pre[j];
+    const uint32_t npx = (uint32_t)J->W * (uint32_t)J->H;
+    const uint32_t inv = inv_gain(ld_dev(&J->num), ld_dev(&J->den), J->glo, J->ghi);
+    const int delta = J->delta, S1 = J->S1;
+    const HueTest h = J->hue;
+    const GLOBAL uint32_t *fr = G(reinterpret_cast<const uint32_t *>(J->frame));
+    const GLOBAL uint32_t *mnp = G(reinterpret_cast<const uint32_t *>(J->bgmin));
+    const GLOBAL uint32_t *mxp = G(reinterpret_cast<const uint32_t *>(J->bgmax));
+    GLOBAL uint64_t *raw = G(J->raw);
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const uint32_t base = ((uint32_t)tile * ITERS + it) * 1024u + (uint32_t)wave * 256u;
+        if (base >= npx)
+            break;
+        const uint32_t p = base + 4u * lane;
+        uint32_t bits = 0;
+        if (p < npx) {
+            const uint32_t q = 3u * (p >> 2);
+            const uint32_t f0 = fr[q], f1 = fr[q + 1], f2 = fr[q + 2];
+            const uint32_t l0 = mnp[q], l1 = mnp[q + 1], l2 = mnp[q + 2];
+            const uint32_t u0 = mxp[q], u1 = mxp[q + 1], u2 = mxp[q + 2];
+            int cv[12];
+            uint32_t out = 0;
+#pragma unroll
+            for (int i = 0; i < 12; ++i) {
+                const int v = (int)corr(byte_of(f0, f1, f2, i), inv);
+                const int lo = (int)byte_of(l0, l1, l2, i) - delta;
+                const int hi = (int)byte_of(u0, u1, u2, i) + delta;
+                cv[i] = v;
+                out |= (uint32_t)((v < lo) | (v > hi)) << (i / 3);
+            }
+            if (out) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (out & (1u << k)) {
+                        const int r = cv[3 * k], g = cv[3 * k + 1], b = cv[3 * k + 2];
+                        const int c = max(max(r, g), b) - min(min(r, g), b);
+                        if (c >= S1 && hue_in(r, g, b, h))
+                            bits |= 1u << k;
+                    }
+                }
+            }
+        }
+        const uint64_t b0 = __ballot(bits & 1u), b1 = __ballot(bits & 2u),
+                       b2 = __ballot(bits & 4u), b3 = __ballot(bits & 8u);
+        if (lane < 4) {
+            const uint32_t word = (base >> 6) + lane;
+            const int sh = 16 * lane;
+            if (word < (npx >> 6))
+                raw[word] = spread4(b0 >> sh) | (spread4(b1 >> sh) << 1) |
+                            (spread4(b2 >> sh) << 2) | (spread4(b3 >> sh) << 3);
+        }
+    }
+}
+
+template <int ITERS>
 __global__ __launch_bounds__(256) void k_classify(Table *__restrict__ T)
 {
     const int nj = T->h.njobs;
     const int total = T->h.cls_pre[nj];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const int j = find_job(T->h.cls_pre, nj, t);
-        const Job *J = &T->jobs[j];
-        const int tile = t - T->h.cls_pre[j];
-        const uint32_t npx = (uint32_t)J->W * (uint32_t)J->H;
-        const uint32_t inv = J->inv;
-        const int delta = J->delta, S1 = J->S1;
-        const HueTest h = J->hue;
-        const uint32_t *fr = reinterpret_cast<const uint32_t *>(J->frame);
-        const uint32_t *mnp = reinterpret_cast<const uint32_t *>(J->bgmin);
-        const uint32_t *mxp = reinterpret_cast<const uint32_t *>(J->bgmax);
-        uint64_t *raw = J->raw;
-#pragma unroll
-        for (int it = 0; it < ITERS; ++it) {
-            const uint32_t base = ((uint32_t)tile * ITERS + it) * 1024u + (uint32_t)wave * 256u;
-            if (base >= npx)
-                break;
-            const uint32_t p = base + 4u * lane;
-            uint32_t bits = 0;
-            if (p < npx) {
-                const uint32_t q = 3u * (p >> 2);
-                const uint32_t f0 = fr[q], f1 = fr[q + 1], f2 = fr[q + 2];
-                const uint32_t l0 = mnp[q], l1 = mnp[q + 1], l2 = mnp[q + 2];
-                const uint32_t u0 = mxp[q], u1 = mxp[q + 1], u2 = mxp[q + 2];
-                int cv[12];
-                uint32_t out = 0;
-#pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    const int v = (int)corr(byte_of(f0, f1, f2, i), inv);
-                    const int lo = (int)byte_of(l0, l1, l2, i) - delta;
-                    const int hi = (int)byte_of(u0, u1, u2, i) + delta;
-                    cv[i] = v;
-                    out |= (uint32_t)((v < lo) | (v > hi)) << (i / 3);
-                }
-                if (out) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        if (out & (1u << k)) {
-                            const int r = cv[3 * k], g = cv[3 * k + 1], b = cv[3 * k + 2];
-                            const int c = max(max(r, g), b) - min(min(r, g), b);
-                            if (c >= S1 && hue_in(r, g, b, h))
-                                bits |= 1u << k;
-                        }
-                    }
-                }
-            }
-            const uint64_t b0 = __ballot(bits & 1u), b1 = __ballot(bits & 2u),
-                           b2 = __ballot(bits & 4u), b3 = __ballot(bits & 8u);
-            if (lane < 4) {
-                const uint32_t word = (base >> 6) + lane;
-                const int sh = 16 * lane;
-                if (word < (npx >> 6))
-                    raw[word] = spread4(b0 >> sh) | (spread4(b1 >> sh) << 1) |
-                                (spread4(b2 >> sh) << 2) | (spread4(b3 >> sh) << 3);
-            }
-        }
-    }
+    for (int t = blockIdx.x; t < total; t += gridDim.x)
+        classify_tile<ITERS>(T, nj, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -347,146 +397,16 @@ __device__ __forceinline__ int run_end_lds(const uint64_t *row, int Wd, int w, i
     return 64 * w + __builtin_ctzll(ends);
 }
 
-template <int R>
-__global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T, int buf_words)
+// A run is packed as (length << 32) | start pixel.
+__device__ __forceinline__ uint2 unpack_run(uint64_t v)
 {
-    extern __shared__ uint64_t lds[];
-    __shared__ uint32_t s_wave[256 / kWave];
-    __shared__ uint32_t s_base;
-    const int nj = T->h.njobs;
-    const int total = T->h.mor_pre[nj];
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const int j = find_job(T->h.mor_pre, nj, t);
-        Job *J = &T->jobs[j];
-        const int band = t - T->h.mor_pre[j];
-        const int W = J->W, H = J->H, Wd = J->Wd;
-        const int oi = J->open_it, ci = J->close_it;
-        const int nops = 2 * (oi + ci);
-        const int y0 = band * R, y1 = min(y0 + R, H);
-        const int ya = max(0, y0 - nops), yb = min(H, y1 + nops);
-        uint64_t *A = lds, *B = lds + buf_words;
-        const uint64_t *src = J->raw + (size_t)ya * Wd;
-        for (int i = threadIdx.x; i < (yb - ya) * Wd; i += blockDim.x)
-            A[i] = src[i];
-        __syncthreads();
-        int va = ya, vb = yb;
-        for (int op = 0; op < nops; ++op) {
-            const bool ero = (op < oi) || (op >= 2 * oi + ci);
-            const uint64_t neutral = ero ? ~0ull : 0ull;
-            const int na = (va == 0) ? 0 : va + 1;
-            const int nb = (vb == H) ? H : vb - 1;
-            for (int i = threadIdx.x; i < (nb - na) * Wd; i += blockDim.x) {
-                const int r = na + i / Wd, w = i - (i / Wd) * Wd;
-                uint64_t v[3];
-#pragma unroll
-                for (int d = -1; d <= 1; ++d) {
-                    const int ww = w + d;
-                    uint64_t acc;
-                    if (ww < 0 || ww >= Wd) {
-                        acc = neutral;
-                    } else {
-                        const uint64_t up = (r - 1 >= 0) ? A[(r - 1 - ya) * Wd + ww] : neutral;
-                        const uint64_t mid = A[(r - ya) * Wd + ww];
-                        const uint64_t dn = (r + 1 < H) ? A[(r + 1 - ya) * Wd + ww] : neutral;
-                        acc = ero ? (up & mid & dn) : (up | mid | dn);
-                    }
-                    v[d + 1] = acc;
-                }
-                const uint64_t left = (v[1] << 1) | (v[0] >> 63);
-                const uint64_t right = (v[1] >> 1) | (v[2] << 63);
-                B[(r - ya) * Wd + w] = ero ? (v[1] & left & right) : (v[1] | left | right);
-            }
-            __syncthreads();
-            uint64_t *tmp = A;
-            A = B;
-            B = tmp;
-            va = na;
-            vb = nb;
-        }
-        // I_FIZI rows of the band
-        const uint64_t *fin = A + (size_t)(y0 - ya) * Wd;
-        uint64_t *dst = J->fizi + (size_t)y0 * Wd;
-        const int nwords = (y1 - y0) * Wd;
-        for (int i = threadIdx.x; i < nwords; i += blockDim.x)
-            dst[i] = fin[i];
-        // runs of the band: count, reserve, emit
-        uint32_t cnt = 0;
-        for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
-            const int w = i % Wd;
-            const uint64_t word = fin[i];
-            const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
-            cnt += (uint32_t)__popcll(word & ~((word << 1) | (prev >> 63)));
-        }
-        uint32_t band_total;
-        uint32_t off = block_excl_scan(cnt, s_wave, &band_total);
-        if (threadIdx.x == 0)
-            s_base = band_total ? atomicAdd(&J->nruns, band_total) : 0u;
-        __syncthreads();
-        uint32_t idx = s_base + off;
-        const uint32_t cap = J->run_cap;
-        if (threadIdx.x == 0 && s_base + band_total > cap)
-            atomicOr(&J->flags, 1u);
-        for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
-            const int rl = i / Wd, w = i - rl * Wd;
-            const uint64_t word = fin[i];
-            const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
-            uint64_t st = word & ~((word << 1) | (prev >> 63));
-            while (st) {
-                const int b = __builtin_ctzll(st);
-                st &= st - 1;
-                const int xs = 64 * w + b;
-                const int xe = run_end_lds(fin + (size_t)rl * Wd, Wd, w, b);
-                const uint32_t start = (uint32_t)(y0 + rl) * (uint32_t)W + (uint32_t)xs;
-                if (idx < cap) {
-                    J->runs[idx] = make_uint2(start, (uint32_t)(xe - xs + 1));
-                    J->parent[start] = start;
-                    J->area[start] = 0u;
-                }
-                ++idx;
-            }
-        }
-        __syncthreads();
-    }
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
 }
 
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t ld_parent(const uint32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint32_t find_root(uint32_t *parent, uint32_t x)
-{
-    uint32_t p = ld_parent(parent + x);
-    while (p != x) {
-        x = p;
-        p = ld_parent(parent + x);
-    }
-    return x;
-}
-
-// Union of the trees of a and b; the smaller label becomes the root, so the
-// root of a finished component is its first run start in raster order.
-__device__ __forceinline__ void unite(uint32_t *parent, uint32_t a, uint32_t b)
-{
-    for (;;) {
-        a = find_root(parent, a);
-        b = find_root(parent, b);
-        if (a == b)
-            return;
-        if (a > b) {
-            const uint32_t t = a;
-            a = b;
-            b = t;
-        }
-        const uint32_t old = atomicMin(parent + b, a);
-        if (old == b)
-            return;
-        b = old;
-    }
-}
-
-__device__ __forceinline__ int next_one(const uint64_t *row, int pos, int limit)
+// Bit scans of one mask row (W = 64 * Wd pixels).
+// First x in [pos, limit] whose bit is 1, or -1.
+template <typename P>
+__device__ __forceinline__ int next_one(P row, int pos, int limit)
 {
     int w = pos >> 6;
     uint64_t m = row[w] & (~0ull << (pos & 63));
@@ -502,7 +422,9 @@ __device__ __forceinline__ int next_one(const uint64_t *row, int pos, int limit)
     }
 }
 
-__device__ __forceinline__ int prev_zero(const uint64_t *row, int pos)
+// Largest x <= pos whose bit is 0, or -1.
+template <typename P>
+__device__ __forceinline__ int prev_zero(P row, int pos)
 {
     int w = pos >> 6;
     const int b = pos & 63;
@@ -516,7 +438,9 @@ __device__ __forceinline__ int prev_zero(const uint64_t *row, int pos)
     return (w << 6) + 63 - __builtin_clzll(m);
 }
 
-__device__ __forceinline__ int next_zero(const uint64_t *row, int Wd, int pos)
+// Smallest x >= pos whose bit is 0, or W.
+template <typename P>
+__device__ __forceinline__ int next_zero(P row, int Wd, int pos)
 {
     int w = pos >> 6;
     uint64_t m = ~row[w] & (~0ull << (pos & 63));
@@ -529,8 +453,209 @@ __device__ __forceinline__ int next_zero(const uint64_t *row, int Wd, int pos)
     return (w << 6) + __builtin_ctzll(m);
 }
 
+// Union-find over run starts (pixel indices). A parent never exceeds its
+// child, so following parents always ends, and the root of a finished
+// component is its smallest run start: its first pixel in raster order.
+__device__ __forceinline__ uint32_t find_root(GLOBAL uint32_t *parent, uint32_t x)
+{
+    uint32_t p = ld_wg(parent + x);
+    while (p != x) {
+        x = p;
+        p = ld_wg(parent + x);
+    }
+    return x;
+}
+
+__device__ __forceinline__ void unite(GLOBAL uint32_t *parent, uint32_t a, uint32_t b)
+{
+    for (;;) {
+        a = find_root(parent, a);
+        b = find_root(parent, b);
+        if (a == b)
+            return;
+        if (a > b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        const uint32_t old = __hip_atomic_fetch_min(parent + b, a, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == b)
+            return;
+        b = old;
+    }
+}
+
+// Joins run (y, xs..xe), whose start pixel is `start`, with every run of the
+// row above that it touches under 8-connectivity (columns xs-1 .. xe+1).
+template <typename P>
+__device__ __forceinline__ void link_up(GLOBAL uint32_t *parent, P above, int Wd, int W, int y,
+                                        int xs, int xe, uint32_t start)
+{
+    const int hi = min(xe + 1, W - 1);
+    int pos = max(xs - 1, 0);
+    while (pos <= hi) {
+        const int xb = next_one(above, pos, hi);
+        if (xb < 0)
+            break;
+        const int bs = prev_zero(above, xb) + 1;
+        unite(parent, start, (uint32_t)(y - 1) * (uint32_t)W + (uint32_t)bs);
+        pos = next_zero(above, Wd, xb) + 1;
+    }
+}
+
+// One workgroup per band of R mask rows: opening and closing in LDS, the
+// band's I_FIZI rows, its runs, and the union-find of the runs inside the
+// band (every run then points straight at its band-local root).
+template <int R>
+__device__ __forceinline__ void morph_tile(Table *__restrict__ T, int nj, int t, uint64_t *lds,
+                                           int buf_words)
+{
+    __shared__ uint32_t s_wave[256 / kWave];
+    __shared__ uint32_t s_base;
+    const int j = find_job(T->h.mor_pre, nj, t);
+    Job *J = &T->jobs[j];
+    const int band = t - T->h.mor_pre[j];
+    const int W = J->W, H = J->H, Wd = J->Wd;
+    const int oi = J->open_it, ci = J->close_it;
+    const int nops = 2 * (oi + ci);
+    const int y0 = band * R, y1 = min(y0 + R, H);
+    const int ya = max(0, y0 - nops), yb = min(H, y1 + nops);
+    uint64_t *A = lds, *B = lds + buf_words;
+    const GLOBAL uint64_t *src = G(J->raw) + (size_t)ya * Wd;
+    for (int i = threadIdx.x; i < (yb - ya) * Wd; i += blockDim.x)
+        A[i] = src[i];
+    __syncthreads();
+    int va = ya, vb = yb;
+    for (int op = 0; op < nops; ++op) {
+        const bool ero = (op < oi) || (op >= 2 * oi + ci);
+        const uint64_t neutral = ero ? ~0ull : 0ull;
+        const int na = (va == 0) ? 0 : va + 1;
+        const int nb = (vb == H) ? H : vb - 1;
+        for (int i = threadIdx.x; i < (nb - na) * Wd; i += blockDim.x) {
+            const int r = na + i / Wd, w = i - (i / Wd) * Wd;
+            uint64_t v[3];
+#pragma unroll
+            for (int d = -1; d <= 1; ++d) {
+                const int ww = w + d;
+                uint64_t acc;
+                if (ww < 0 || ww >= Wd) {
+                    acc = neutral;
+                } else {
+                    const uint64_t up = (r - 1 >= 0) ? A[(r - 1 - ya) * Wd + ww] : neutral;
+                    const uint64_t mid = A[(r - ya) * Wd + ww];
+                    const uint64_t dn = (r + 1 < H) ? A[(r + 1 - ya) * Wd + ww] : neutral;
+                    acc = ero ? (up & mid & dn) : (up | mid | dn);
+                }
+                v[d + 1] = acc;
+            }
+            const uint64_t left = (v[1] << 1) | (v[0] >> 63);
+            const uint64_t right = (v[1] >> 1) | (v[2] << 63);
+            B[(r - ya) * Wd + w] = ero ? (v[1] & left & right) : (v[1] | left | right);
+        }
+        __syncthreads();
+        uint64_t *tmp = A;
+        A = B;
+        B = tmp;
+        va = na;
+        vb = nb;
+    }
+    // I_FIZI rows of the band
+    const uint64_t *fin = A + (size_t)(y0 - ya) * Wd;
+    GLOBAL uint64_t *dst = G(J->fizi) + (size_t)y0 * Wd;
+    const int nwords = (y1 - y0) * Wd;
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x)
+        dst[i] = fin[i];
+    // runs of the band: count, reserve, emit
+    uint32_t cnt = 0;
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+        const int w = i % Wd;
+        const uint64_t word = fin[i];
+        const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
+        cnt += (uint32_t)__popcll(word & ~((word << 1) | (prev >> 63)));
+    }
+    uint32_t band_total;
+    uint32_t off = block_excl_scan(cnt, s_wave, &band_total);
+    if (threadIdx.x == 0)
+        s_base = band_total ? atomicAdd(&J->nruns, band_total) : 0u;
+    __syncthreads();
+    uint32_t idx = s_base + off;
+    const uint32_t cap = J->run_cap;
+    if (threadIdx.x == 0 && s_base + band_total > cap)
+        atomicOr(&J->flags, 1u);
+    GLOBAL uint32_t *parent = G(J->parent);
+    GLOBAL uint32_t *area = G(J->area);
+    GLOBAL uint64_t *runs = G(reinterpret_cast<uint64_t *>(J->runs));
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+        const int rl = i / Wd, w = i - rl * Wd;
+        const uint64_t word = fin[i];
+        const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
+        uint64_t st = word & ~((word << 1) | (prev >> 63));
+        while (st) {
+            const int b = __builtin_ctzll(st);
+            st &= st - 1;
+            const int xs = 64 * w + b;
+            const int xe = run_end_lds(fin + (size_t)rl * Wd, Wd, w, b);
+            const uint32_t start = (uint32_t)(y0 + rl) * (uint32_t)W + (uint32_t)xs;
+            if (idx < cap) {
+                runs[idx] = ((uint64_t)(uint32_t)(xe - xs + 1) << 32) | start;
+                st_wg(parent + start, start);
+                area[start] = 0u;
+            }
+            ++idx;
+        }
+    }
+    __syncthreads();
+    // union-find inside the band: each run below the band's first row
+    // joins the runs it touches in the row above
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+        const int rl = i / Wd, w = i - rl * Wd;
+        if (rl == 0)
+            continue;
+        const uint64_t word = fin[i];
+        const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
+        uint64_t st = word & ~((word << 1) | (prev >> 63));
+        while (st) {
+            const int b = __builtin_ctzll(st);
+            st &= st - 1;
+            const int xs = 64 * w + b;
+            const int xe = run_end_lds(fin + (size_t)rl * Wd, Wd, w, b);
+            const uint32_t start = (uint32_t)(y0 + rl) * (uint32_t)W + (uint32_t)xs;
+            link_up(parent, fin + (size_t)(rl - 1) * Wd, Wd, W, y0 + rl, xs, xe, start);
+        }
+    }
+    __syncthreads();
+    // every run of the band points at its band root
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+        const int rl = i / Wd, w = i - rl * Wd;
+        const uint64_t word = fin[i];
+        const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
+        uint64_t st = word & ~((word << 1) | (prev >> 63));
+        while (st) {
+            const int b = __builtin_ctzll(st);
+            st &= st - 1;
+            const uint32_t start = (uint32_t)(y0 + rl) * (uint32_t)W + (uint32_t)(64 * w + b);
+            const uint32_t root = find_root(parent, start);
+            if (root != start)
+                st_wg(parent + start, root);
+        }
+    }
+    __syncthreads();
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T, int buf_words)
+{
+    extern __shared__ uint64_t lds[];
+    const int nj = T->h.njobs;
+    const int total = T->h.mor_pre[nj];
+    for (int t = blockIdx.x; t < total; t += gridDim.x)
+        morph_tile<R>(T, nj, t, lds, buf_words);
+}
+
+// ---------------------------------------------------------------------------
 constexpr int kResolveThreads = 512;
-constexpr int kResolveWaves = kResolveThreads / kWave;
+constexpr int kMaxWaves = 16;
 
 template <typename T, typename Op>
 __device__ __forceinline__ T block_reduce(T v, T *s, Op op)
@@ -543,7 +668,7 @@ __device__ __forceinline__ T block_reduce(T v, T *s, Op op)
         s[wave] = v;
     __syncthreads();
     T r = s[0];
-    for (int w = 1; w < kResolveWaves; ++w)
+    for (int w = 1; w < (int)(blockDim.x / kWave); ++w)
         r = op(r, s[w]);
     __syncthreads();
     return r;
@@ -553,131 +678,191 @@ struct OpAdd { template <typename T> __device__ T operator()(T a, T b) const { r
 struct OpMax { template <typename T> __device__ T operator()(T a, T b) const { return a > b ? a : b; } };
 struct OpMin { template <typename T> __device__ T operator()(T a, T b) const { return a < b ? a : b; } };
 
-__global__ __launch_bounds__(kResolveThreads) void k_resolve(Table *__restrict__ T)
+// One workgroup per frame: joins the band-local trees across band borders,
+// then finds roots, areas, the hand zone (largest area, ties to the smallest
+// first index), its sums and box, and writes the pointer.
+__device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j)
 {
-    __shared__ unsigned long long s_u64[kResolveWaves];
-    __shared__ uint32_t s_u32[kResolveWaves];
-    const int nj = T->h.njobs;
-    for (int j = blockIdx.x; j < nj; j += gridDim.x) {
-        Job *J = &T->jobs[j];
-        const int W = J->W, H = J->H, Wd = J->Wd;
-        const uint32_t nr = min(J->nruns, J->run_cap);
-        const uint2 *runs = J->runs;
-        uint32_t *parent = J->parent;
-        uint32_t *area = J->area;
-        const uint64_t *fz = J->fizi;
-        uint64_t *hand = J->hand;
-        if (hand)
-            for (int i = threadIdx.x; i < H * Wd; i += blockDim.x)
-                hand[i] = 0ull;
-        // A: link every run to the runs it touches in the row above
+    __shared__ unsigned long long s_u64[kMaxWaves];
+    __shared__ uint32_t s_u32[kMaxWaves];
+    Job *J = &T->jobs[j];
+    const int W = J->W, H = J->H, Wd = J->Wd, band = J->band;
+    const uint32_t nr = min(ld_dev(&J->nruns), J->run_cap);
+    const GLOBAL uint64_t *runs = G(reinterpret_cast<const uint64_t *>(J->runs));
+    GLOBAL uint32_t *parent = G(J->parent);
+    GLOBAL uint32_t *area = G(J->area);
+    const GLOBAL uint64_t *fz = G(J->fizi);
+    GLOBAL uint64_t *hand = J->hand ? G(J->hand) : nullptr;
+    const uint32_t inv = inv_gain(ld_dev(&J->num), ld_dev(&J->den), J->glo, J->ghi);
+    if (hand)
+        for (int i = threadIdx.x; i < H * Wd; i += blockDim.x)
+            hand[i] = 0ull;
+    // A: runs on the first row of a band join the band above
+    for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+        const uint2 rn = unpack_run(runs[i]);
+        const int y = (int)(rn.x / (uint32_t)W);
+        if (y == 0 || y % band != 0)
+            continue;
+        const int xs = (int)(rn.x - (uint32_t)y * W), xe = xs + (int)rn.y - 1;
+        link_up(parent, fz + (size_t)(y - 1) * Wd, Wd, W, y, xs, xe, rn.x);
+    }
+    __syncthreads();
+    // B: roots and areas
+    uint32_t ncomp = 0;
+    for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+        const uint2 rn = unpack_run(runs[i]);
+        const uint32_t root = find_root(parent, rn.x);
+        if (root == rn.x)
+            ++ncomp;
+        else
+            st_wg(parent + rn.x, root);
+        __hip_atomic_fetch_add(area + root, rn.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    // C: the largest component, ties to the smallest first index
+    unsigned long long best = 0ull;
+    for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+        const uint32_t s = (uint32_t)runs[i];
+        if (ld_wg(parent + s) == s) {
+            const unsigned long long key = ((unsigned long long)ld_wg(area + s) << 32) | (0xFFFFFFFFull - s);
+            best = key > best ? key : best;
+        }
+    }
+    best = block_reduce<unsigned long long>(best, s_u64, OpMax());
+    ncomp = block_reduce<uint32_t>(ncomp, s_u32, OpAdd());
+    const uint32_t A = (uint32_t)(best >> 32);
+    const uint32_t kstar = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
+    const bool present = ncomp > 0 && (long long)A >= (long long)J->min_area;
+    // D: sums and box of the selected component
+    unsigned long long sx = 0, sy = 0;
+    uint32_t x0 = 0xFFFFFFFFu, y0 = 0xFFFFFFFFu, x1 = 0, y1 = 0;
+    if (present) {
         for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
-            const uint2 rn = runs[i];
-            const int y = (int)(rn.x / (uint32_t)W);
-            if (y == 0)
+            const uint2 rn = unpack_run(runs[i]);
+            if (ld_wg(parent + rn.x) != kstar)
                 continue;
-            const int xs = (int)(rn.x - (uint32_t)y * W), xe = xs + (int)rn.y - 1;
-            const uint64_t *above = fz + (size_t)(y - 1) * Wd;
-            const int hi = min(xe + 1, W - 1);
-            int pos = max(xs - 1, 0);
-            while (pos <= hi) {
-                const int xb = next_one(above, pos, hi);
-                if (xb < 0)
-                    break;
-                const int bs = prev_zero(above, xb) + 1;
-                unite(parent, rn.x, (uint32_t)(y - 1) * W + (uint32_t)bs);
-                pos = next_zero(above, Wd, xb) + 1;
-            }
-        }
-        __threadfence();
-        __syncthreads();
-        // B: roots and areas
-        uint32_t ncomp = 0;
-        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
-            const uint2 rn = runs[i];
-            const uint32_t root = find_root(parent, rn.x);
-            if (root == rn.x)
-                ++ncomp;
-            else
-                __hip_atomic_store(parent + rn.x, root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            atomicAdd(area + root, rn.y);
-        }
-        __threadfence();
-        __syncthreads();
-        // C: the largest component, ties to the smallest first index
-        unsigned long long best = 0ull;
-        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
-            const uint32_t s = runs[i].x;
-            if (ld_parent(parent + s) == s) {
-                const uint32_t a = __hip_atomic_load(area + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long key = ((unsigned long long)a << 32) | (0xFFFFFFFFull - s);
-                best = key > best ? key : best;
-            }
-        }
-        best = block_reduce<unsigned long long>(best, s_u64, OpMax());
-        ncomp = block_reduce<uint32_t>(ncomp, s_u32, OpAdd());
-        const uint32_t A = (uint32_t)(best >> 32);
-        const uint32_t kstar = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
-        const bool present = ncomp > 0 && (long long)A >= (long long)J->min_area;
-        // D: sums and box of the selected component
-        unsigned long long sx = 0, sy = 0;
-        uint32_t x0 = 0xFFFFFFFFu, y0 = 0xFFFFFFFFu, x1 = 0, y1 = 0;
-        if (present) {
-            for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
-                const uint2 rn = runs[i];
-                if (ld_parent(parent + rn.x) != kstar)
-                    continue;
-                const uint32_t y = rn.x / (uint32_t)W, xs = rn.x - y * (uint32_t)W;
-                const uint32_t xe = xs + rn.y - 1;
-                sx += (unsigned long long)rn.y * xs + (unsigned long long)rn.y * (rn.y - 1) / 2;
-                sy += (unsigned long long)rn.y * y;
-                x0 = min(x0, xs);
-                x1 = max(x1, xe);
-                y0 = min(y0, y);
-                y1 = max(y1, y);
-                if (hand) {
-                    uint64_t *hr = hand + (size_t)y * Wd;
-                    const int wa = (int)(xs >> 6), wb = (int)(xe >> 6);
-                    for (int w = wa; w <= wb; ++w) {
-                        const int lo = (w == wa) ? (int)(xs & 63) : 0;
-                        const int hi = (w == wb) ? (int)(xe & 63) : 63;
-                        const uint64_t m = (hi == 63 ? ~0ull : ((2ull << hi) - 1ull)) & (~0ull << lo);
-                        atomicOr(reinterpret_cast<unsigned long long *>(hr + w), (unsigned long long)m);
-                    }
+            const uint32_t y = rn.x / (uint32_t)W, xs = rn.x - y * (uint32_t)W;
+            const uint32_t xe = xs + rn.y - 1;
+            sx += (unsigned long long)rn.y * xs + (unsigned long long)rn.y * (rn.y - 1) / 2;
+            sy += (unsigned long long)rn.y * y;
+            x0 = min(x0, xs);
+            x1 = max(x1, xe);
+            y0 = min(y0, y);
+            y1 = max(y1, y);
+            if (hand) {
+                GLOBAL uint64_t *hr = hand + (size_t)y * Wd;
+                const int wa = (int)(xs >> 6), wb = (int)(xe >> 6);
+                for (int w = wa; w <= wb; ++w) {
+                    const int lo = (w == wa) ? (int)(xs & 63) : 0;
+                    const int hi = (w == wb) ? (int)(xe & 63) : 63;
+                    const uint64_t m = (hi == 63 ? ~0ull : ((2ull << hi) - 1ull)) & (~0ull << lo);
+                    __hip_atomic_fetch_or(hr + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
         }
-        sx = block_reduce<unsigned long long>(sx, s_u64, OpAdd());
-        sy = block_reduce<unsigned long long>(sy, s_u64, OpAdd());
-        x0 = block_reduce<uint32_t>(x0, s_u32, OpMin());
-        y0 = block_reduce<uint32_t>(y0, s_u32, OpMin());
-        x1 = block_reduce<uint32_t>(x1, s_u32, OpMax());
-        y1 = block_reduce<uint32_t>(y1, s_u32, OpMax());
-        if (threadIdx.x == 0) {
-            fizi_pointer o;
-            o.present = present ? 1 : 0;
-            o.click = 0;
-            o.reserved = 0;
-            o.area = 0;
-            o.sum_x = o.sum_y = 0;
-            o.x0 = o.y0 = o.x1 = o.y1 = 0;
-            if (present) {
-                o.area = A;
-                o.sum_x = sx;
-                o.sum_y = sy;
-                o.x0 = x0;
-                o.y0 = y0;
-                o.x1 = x1;
-                o.y1 = y1;
-                const unsigned long long box = (unsigned long long)(x1 - x0 + 1) * (y1 - y0 + 1);
-                o.click = (1000ull * A >= (unsigned long long)J->fill_pm * box) ? 1 : 0;
-            }
-            o.n_components = ncomp;
-            o.inv_gain_q16 = J->inv;
-            o.frame_index = J->frame_index;
-            *J->out = o;
+    }
+    sx = block_reduce<unsigned long long>(sx, s_u64, OpAdd());
+    sy = block_reduce<unsigned long long>(sy, s_u64, OpAdd());
+    x0 = block_reduce<uint32_t>(x0, s_u32, OpMin());
+    y0 = block_reduce<uint32_t>(y0, s_u32, OpMin());
+    x1 = block_reduce<uint32_t>(x1, s_u32, OpMax());
+    y1 = block_reduce<uint32_t>(y1, s_u32, OpMax());
+    if (threadIdx.x == 0) {
+        fizi_pointer o;
+        o.present = present ? 1 : 0;
+        o.click = 0;
+        o.reserved = 0;
+        o.area = 0;
+        o.sum_x = o.sum_y = 0;
+        o.x0 = o.y0 = o.x1 = o.y1 = 0;
+        if (present) {
+            o.area = A;
+            o.sum_x = sx;
+            o.sum_y = sy;
+            o.x0 = x0;
+            o.y0 = y0;
+            o.x1 = x1;
+            o.y1 = y1;
+            const unsigned long long box = (unsigned long long)(x1 - x0 + 1) * (y1 - y0 + 1);
+            o.click = (1000ull * A >= (unsigned long long)J->fill_pm * box) ? 1 : 0;
         }
-        __syncthreads();
+        o.n_components = ncomp;
+        o.inv_gain_q16 = inv;
+        o.frame_index = J->frame_index;
+        *J->out = o;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kResolveThreads) void k_resolve(Table *__restrict__ T)
+{
+    const int nj = T->h.njobs;
+    for (int j = blockIdx.x; j < nj; j += gridDim.x)
+        resolve_job(T, j);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent fused step: the four stages of one frame step in one launch,
+// separated by grid-wide barriers. The grid never exceeds the blocks that can
+// be resident at once. Every wait is bounded: a block that waits too long
+// sets the error word and skips the remaining stages, so every block reaches
+// the end of the kernel; the last block to finish resets the counters for the
+// next launch.
+constexpr unsigned kSpinLimit = 1u << 20;
+
+__device__ __forceinline__ bool grid_sync(PersistState *ps, unsigned k)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // release this block's writes to the other blocks
+        atomicAdd(&ps->arrived, 1u);
+        const unsigned target = k * gridDim.x;
+        unsigned spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(&ps->arrived, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kSpinLimit) {
+                atomicOr(&ps->error, 1u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (__hip_atomic_load(&ps->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            ok = 0;
+        __threadfence();   // acquire the other blocks' writes
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <int ITERS, int R>
+__global__ __launch_bounds__(256) void k_step(Table *__restrict__ T, int buf_words, PersistState *ps)
+{
+    extern __shared__ uint64_t lds[];
+    const int nj = T->h.njobs;
+    for (int t = blockIdx.x; t < T->h.gain_pre[nj]; t += gridDim.x)
+        gain_tile(T, nj, t);
+    bool ok = grid_sync(ps, 1);
+    if (ok)
+        for (int t = blockIdx.x; t < T->h.cls_pre[nj]; t += gridDim.x)
+            classify_tile<ITERS>(T, nj, t);
+    ok = grid_sync(ps, 2) && ok;
+    if (ok)
+        for (int t = blockIdx.x; t < T->h.mor_pre[nj]; t += gridDim.x)
+            morph_tile<R>(T, nj, t, lds, buf_words);
+    ok = grid_sync(ps, 3) && ok;
+    if (ok)
+        for (int j = blockIdx.x; j < nj; j += gridDim.x)
+            resolve_job(T, j);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned done = atomicAdd(&ps->finished, 1u);
+        if (done == gridDim.x - 1) {
+            __hip_atomic_store(&ps->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ps->finished, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -690,6 +875,17 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n)
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Launches go through hipExtLaunchKernelGGL so that, when the caller asks for
+// it, the start/stop events are taken from the kernel's own dispatch.
+#define FIZI_LAUNCH(kern, grid, block, lds, s, ev, ...)                                              \
+    do {                                                                                           \
+        if ((ev).start || (ev).stop)                                                               \
+            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, (ev).start, (ev).stop, 0, \
+                                  __VA_ARGS__);                                                    \
+        else                                                                                       \
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, __VA_ARGS__);                \
+    } while (0)
+
 hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H, int rs, hipStream_t s)
 {
     const int rows = (H + rs - 1) / rs;
@@ -699,64 +895,116 @@ hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H,
     return hipGetLastError();
 }
 
-hipError_t launch_gain(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t, hipStream_t s)
+hipError_t launch_gain(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t, hipStream_t s,
+                       StageEvents ev)
 {
     if (total_tiles <= 0)
         return hipSuccess;
     const int grid = min(total_tiles, n_cu * t.grid_per_cu);
-    k_gain<<<grid, 256, 0, s>>>(const_cast<Table *>(d_tab));
+    FIZI_LAUNCH(k_gain, grid, 256, 0, s, ev, const_cast<Table *>(d_tab));
     return hipGetLastError();
 }
 
 hipError_t launch_minmax(const Table *d_tab, int njobs, uint8_t *bgmin, uint8_t *bgmax, int npx,
-                         int reset, int n_cu, hipStream_t s)
+                         int reset, int n_cu, hipStream_t s, StageEvents ev)
 {
     const int groups = npx / 4;
     const int grid = min((groups + 255) / 256, n_cu * 8);
-    k_minmax<<<grid, 256, 0, s>>>(const_cast<Table *>(d_tab), njobs, bgmin, bgmax, npx, reset);
+    FIZI_LAUNCH(k_minmax, grid, 256, 0, s, ev, const_cast<Table *>(d_tab), njobs, bgmin, bgmax, npx,
+                reset);
     return hipGetLastError();
 }
 
-hipError_t launch_classify(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t, hipStream_t s)
+hipError_t launch_classify(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t, hipStream_t s,
+                           StageEvents ev)
 {
     if (total_tiles <= 0)
         return hipSuccess;
     const int grid = min(total_tiles, n_cu * t.grid_per_cu);
     Table *tab = const_cast<Table *>(d_tab);
     switch (t.cls_iters) {
-    case 1: k_classify<1><<<grid, 256, 0, s>>>(tab); break;
-    case 2: k_classify<2><<<grid, 256, 0, s>>>(tab); break;
-    case 8: k_classify<8><<<grid, 256, 0, s>>>(tab); break;
-    default: k_classify<4><<<grid, 256, 0, s>>>(tab); break;
+    case 1: FIZI_LAUNCH(k_classify<1>, grid, 256, 0, s, ev, tab); break;
+    case 2: FIZI_LAUNCH(k_classify<2>, grid, 256, 0, s, ev, tab); break;
+    case 8: FIZI_LAUNCH(k_classify<8>, grid, 256, 0, s, ev, tab); break;
+    default: FIZI_LAUNCH(k_classify<4>, grid, 256, 0, s, ev, tab); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max_ops, int n_cu,
-                        const Tuning &t, hipStream_t s)
+                        const Tuning &t, hipStream_t s, StageEvents ev)
 {
     if (total_tiles <= 0)
         return hipSuccess;
     const int rows = t.morph_rows + 2 * max_ops;
     const int buf_words = rows * max_wd;
-    const size_t lds = 2 * (size_t)buf_words * sizeof(uint64_t);
+    const uint32_t lds = (uint32_t)(2 * (size_t)buf_words * sizeof(uint64_t));
     const int grid = min(total_tiles, n_cu * 4);
     Table *tab = const_cast<Table *>(d_tab);
     switch (t.morph_rows) {
-    case 8: k_morph<8><<<grid, 256, lds, s>>>(tab, buf_words); break;
-    case 16: k_morph<16><<<grid, 256, lds, s>>>(tab, buf_words); break;
-    case 64: k_morph<64><<<grid, 256, lds, s>>>(tab, buf_words); break;
-    default: k_morph<32><<<grid, 256, lds, s>>>(tab, buf_words); break;
+    case 8: FIZI_LAUNCH(k_morph<8>, grid, 256, lds, s, ev, tab, buf_words); break;
+    case 16: FIZI_LAUNCH(k_morph<16>, grid, 256, lds, s, ev, tab, buf_words); break;
+    case 64: FIZI_LAUNCH(k_morph<64>, grid, 256, lds, s, ev, tab, buf_words); break;
+    default: FIZI_LAUNCH(k_morph<32>, grid, 256, lds, s, ev, tab, buf_words); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s)
+hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev)
 {
     if (njobs <= 0)
         return hipSuccess;
-    k_resolve<<<njobs, kResolveThreads, 0, s>>>(const_cast<Table *>(d_tab));
+    FIZI_LAUNCH(k_resolve, njobs, kResolveThreads, 0, s, ev, const_cast<Table *>(d_tab));
     return hipGetLastError();
+}
+
+// Blocks per CU of the persistent step: what the kernel's registers and LDS
+// allow (wave64, 512 VGPRs per SIMD lane in granules of 8, four SIMDs and
+// 160 KiB of LDS per CU, eight waves per SIMD), capped at four so that the
+// whole grid is resident with room to spare.
+template <int ITERS, int R>
+int step_blocks_per_cu(uint32_t lds)
+{
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(k_step<ITERS, R>)) != hipSuccess)
+        return 1;
+    const int vgpr = std::max(8, (a.numRegs + 7) / 8 * 8);
+    const int waves_per_simd = std::min(8, 512 / vgpr);     // one wave of each block per SIMD
+    const int by_lds = (int)((160 * 1024) / std::max<size_t>(1, lds + a.sharedSizeBytes));
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<ITERS, R>, 256, lds) != hipSuccess)
+        nb = 1;
+    return std::max(1, std::min(std::min(nb, 4), std::min(waves_per_simd, by_lds)));
+}
+
+template <int ITERS, int R>
+hipError_t launch_step_t(Table *tab, int buf_words, uint32_t lds, int n_cu, PersistState *ps, hipStream_t s,
+                         StageEvents ev)
+{
+    static int per_cu = -1;
+    static uint32_t per_cu_lds = 0;
+    if (per_cu < 0 || per_cu_lds != lds) {
+        per_cu = step_blocks_per_cu<ITERS, R>(lds);
+        per_cu_lds = lds;
+    }
+    FIZI_LAUNCH((k_step<ITERS, R>), per_cu * n_cu, 256, lds, s, ev, tab, buf_words, ps);
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(const Table *d_tab, int max_wd, int max_ops, int n_cu, const Tuning &t,
+                             uint8_t *persist, hipStream_t s, StageEvents ev)
+{
+    const int rows = t.morph_rows + 2 * max_ops;
+    const int buf_words = rows * max_wd;
+    const uint32_t lds = (uint32_t)(2 * (size_t)buf_words * sizeof(uint64_t));
+    Table *tab = const_cast<Table *>(d_tab);
+    PersistState *ps = reinterpret_cast<PersistState *>(persist);
+    switch (t.morph_rows) {
+    case 8: return launch_step_t<4, 8>(tab, buf_words, lds, n_cu, ps, s, ev);
+    case 16: return launch_step_t<4, 16>(tab, buf_words, lds, n_cu, ps, s, ev);
+    case 64: return launch_step_t<4, 64>(tab, buf_words, lds, n_cu, ps, s, ev);
+    default: return launch_step_t<4, 32>(tab, buf_words, lds, n_cu, ps, s, ev);
+    }
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s)

@@ -1,0 +1,255 @@
+// Soft (sigmoid-relaxed) skin mask for calibration, with its hand-written
+// adjoint: m = sigmoid((theta - d) / T), d the Mahalanobis distance of the
+// pixel's BT.601 chroma (Cb, Cr) from (mu_b, mu_r) under the covariance
+// [[s_bb, s_br], [s_br, s_rr]]. Per-pixel arithmetic in FP32; gradient and
+// loss sums in FP64, reduced in a fixed order (bitwise reproducible).
+#include <cmath>
+
+#include "fizi_host.h"
+
+namespace fizi {
+namespace {
+
+constexpr int kSoftBlocksMax = 2048;
+constexpr int kSoftOut = 8;        // 6 gradients, loss, unused
+
+struct SoftParams {
+    float mu_b, mu_r;
+    float p_bb, p_br, p_rr;        // inverse covariance
+    float theta, inv_t;
+};
+
+struct SoftPx {
+    float m, z, d, ub, ur;
+};
+
+__device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftParams &s)
+{
+    const float cb = fmaf(0.5f, b, fmaf(-0.331264f, g, fmaf(-0.168736f, r, 128.0f)));
+    const float cr = fmaf(-0.081312f, b, fmaf(-0.418688f, g, fmaf(0.5f, r, 128.0f)));
+    const float db = cb - s.mu_b, dr = cr - s.mu_r;
+    SoftPx o;
+    o.ub = fmaf(s.p_bb, db, s.p_br * dr);
+    o.ur = fmaf(s.p_br, db, s.p_rr * dr);
+    o.d = sqrtf(fmaxf(fmaf(db, o.ub, dr * o.ur), 0.0f));
+    o.z = (s.theta - o.d) * s.inv_t;
+    o.m = 1.0f / (1.0f + expf(-o.z));
+    return o;
+}
+
+__device__ __forceinline__ uint32_t byte_at(uint32_t w0, uint32_t w1, uint32_t w2, int i)
+{
+    const uint32_t w = i < 4 ? w0 : (i < 8 ? w1 : w2);
+    return (w >> (8 * (i & 3))) & 0xFFu;
+}
+
+__global__ __launch_bounds__(256) void k_soft_fwd(const uint8_t *__restrict__ frames, long long npx, SoftParams s,
+                                                  float *__restrict__ mask)
+{
+    const long long groups = npx / 4;
+    const uint32_t *f = reinterpret_cast<const uint32_t *>(frames);
+    for (long long gi = blockIdx.x * (long long)blockDim.x + threadIdx.x; gi < groups;
+         gi += (long long)gridDim.x * blockDim.x) {
+        const uint32_t w0 = f[3 * gi], w1 = f[3 * gi + 1], w2 = f[3 * gi + 2];
+        float4 out;
+        out.x = soft_px(byte_at(w0, w1, w2, 0), byte_at(w0, w1, w2, 1), byte_at(w0, w1, w2, 2), s).m;
+        out.y = soft_px(byte_at(w0, w1, w2, 3), byte_at(w0, w1, w2, 4), byte_at(w0, w1, w2, 5), s).m;
+        out.z = soft_px(byte_at(w0, w1, w2, 6), byte_at(w0, w1, w2, 7), byte_at(w0, w1, w2, 8), s).m;
+        out.w = soft_px(byte_at(w0, w1, w2, 9), byte_at(w0, w1, w2, 10), byte_at(w0, w1, w2, 11), s).m;
+        reinterpret_cast<float4 *>(mask)[gi] = out;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)(npx - 4 * groups)) {
+        const long long i = 4 * groups + threadIdx.x;
+        mask[i] = soft_px(frames[3 * i], frames[3 * i + 1], frames[3 * i + 2], s).m;
+    }
+}
+
+// Adds one pixel's contributions: dL/dz is gz; its loss term when y >= 0.
+__device__ __forceinline__ void soft_acc(const SoftPx &o, float gz, float inv_t, double *acc)
+{
+    const float gd = -gz * inv_t;
+    const float gq = o.d > 0.0f ? gd / (2.0f * o.d) : 0.0f;
+    acc[0] += (double)(gq * (-2.0f * o.ub));
+    acc[1] += (double)(gq * (-2.0f * o.ur));
+    acc[2] += (double)(gq * (-o.ub * o.ub));
+    acc[3] += (double)(gq * (-2.0f * o.ub * o.ur));
+    acc[4] += (double)(gq * (-o.ur * o.ur));
+    acc[5] += (double)(gz * inv_t);
+}
+
+// dL/dz of one pixel: from the upstream dL/dm, or (fused BCE) (m - y) / N,
+// which also adds the pixel's BCE term to acc[6].
+__device__ __forceinline__ float soft_gz(const SoftPx &o, const float *dLdm, const uint8_t *gt, long long i,
+                                         float inv_n, double *acc)
+{
+    if (dLdm)
+        return dLdm[i] * o.m * (1.0f - o.m);
+    const float y = gt[i] ? 1.0f : 0.0f;
+    acc[6] += (double)(fmaxf(o.z, 0.0f) - o.z * y + log1pf(expf(-fabsf(o.z))));
+    return (o.m - y) * inv_n;
+}
+
+__global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ frames, const float *__restrict__ dLdm,
+                                                  const uint8_t *__restrict__ gt, long long npx, SoftParams s,
+                                                  float inv_n, double *__restrict__ partial)
+{
+    __shared__ double s_red[256 / 64][kSoftOut];
+    double acc[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const long long groups = npx / 4;
+    const uint32_t *f = reinterpret_cast<const uint32_t *>(frames);
+    for (long long gi = blockIdx.x * (long long)blockDim.x + threadIdx.x; gi < groups;
+         gi += (long long)gridDim.x * blockDim.x) {
+        const uint32_t w0 = f[3 * gi], w1 = f[3 * gi + 1], w2 = f[3 * gi + 2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const SoftPx o = soft_px(byte_at(w0, w1, w2, 3 * k), byte_at(w0, w1, w2, 3 * k + 1),
+                                     byte_at(w0, w1, w2, 3 * k + 2), s);
+            soft_acc(o, soft_gz(o, dLdm, gt, 4 * gi + k, inv_n, acc), s.inv_t, acc);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)(npx - 4 * groups)) {
+        const long long i = 4 * groups + threadIdx.x;
+        const SoftPx o = soft_px(frames[3 * i], frames[3 * i + 1], frames[3 * i + 2], s);
+        soft_acc(o, soft_gz(o, dLdm, gt, i, inv_n, acc), s.inv_t, acc);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x / 64;
+#pragma unroll
+    for (int k = 0; k < kSoftOut; ++k) {
+        double v = acc[k];
+        for (int o = 32; o > 0; o >>= 1)
+            v += __shfl_xor(v, o, 64);
+        if (lane == 0)
+            s_red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kSoftOut) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w)
+            v += s_red[w][threadIdx.x];
+        partial[blockIdx.x * kSoftOut + threadIdx.x] = v;
+    }
+}
+
+// Fixed-order sum of the block partials: out[k] = sum_b partial[b][k] * scale[k].
+__global__ __launch_bounds__(256) void k_soft_final(const double *__restrict__ partial, int nblocks, double loss_scale,
+                                                    double *__restrict__ out, int nout)
+{
+    __shared__ double s[256];
+    for (int k = 0; k < nout; ++k) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+            v += partial[b * kSoftOut + k];
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h)
+                s[threadIdx.x] += s[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            out[k] = k == 6 ? s[0] * loss_scale : s[0];
+        __syncthreads();
+    }
+}
+
+int soft_params(const float p6[6], float T, SoftParams *s)
+{
+    if (!p6)
+        return fail(FIZI_EINVAL, "null parameters");
+    const double sbb = p6[2], sbr = p6[3], srr = p6[4];
+    const double det = sbb * srr - sbr * sbr;
+    if (!(det > 0.0) || !(sbb > 0.0))
+        return fail(FIZI_EINVAL, "covariance must be positive definite");
+    if (!(T > 0.0f) || !std::isfinite(T))
+        return fail(FIZI_EINVAL, "temperature must be positive");
+    s->mu_b = p6[0];
+    s->mu_r = p6[1];
+    s->p_bb = (float)(srr / det);
+    s->p_br = (float)(-sbr / det);
+    s->p_rr = (float)(sbb / det);
+    s->theta = p6[5];
+    s->inv_t = 1.0f / T;
+    return FIZI_OK;
+}
+
+int soft_grid(long long npx)
+{
+    int dev = 0, n_cu = 0;
+    if (device_cu_count(&dev, &n_cu) != FIZI_OK)
+        n_cu = 256;
+    const long long groups = (npx / 4 + 255) / 256;
+    return (int)std::max<long long>(1, std::min<long long>(std::min(kSoftBlocksMax, n_cu * 4), groups));
+}
+
+int soft_backward(const uint8_t *frames, const float *dLdm, const uint8_t *gt, long long npx, const float p6[6],
+                  float T, void *ws, size_t ws_bytes, double *out, int nout, void *stream)
+{
+    if (!frames || !out || !ws || (!dLdm && !gt))
+        return fail(FIZI_EINVAL, "null argument");
+    if (npx < 1)
+        return fail(FIZI_EINVAL, "npx must be >= 1");
+    if (reinterpret_cast<uintptr_t>(frames) % 4 != 0 || (dLdm && reinterpret_cast<uintptr_t>(dLdm) % 4 != 0))
+        return fail(FIZI_EINVAL, "frames and dL/dm must be 4-byte aligned");
+    if (ws_bytes < (size_t)kSoftBlocksMax * kSoftOut * sizeof(double))
+        return fail(FIZI_ENOMEM, "workspace smaller than fizi_soft_workspace_bytes()");
+    SoftParams s;
+    FIZI_TRY(soft_params(p6, T, &s));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = soft_grid(npx);
+    double *partial = static_cast<double *>(ws);
+    k_soft_bwd<<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, (float)(1.0 / (double)npx), partial);
+    FIZI_HIP(hipGetLastError());
+    k_soft_final<<<1, 256, 0, st>>>(partial, grid, 1.0 / (double)npx, out, nout);
+    FIZI_HIP(hipGetLastError());
+    return FIZI_OK;
+}
+
+}  // namespace
+}  // namespace fizi
+
+using namespace fizi;
+
+extern "C" {
+
+int fizi_soft_forward(const uint8_t *d_frames, int64_t npx, const float params6[6], float T, float *d_mask,
+                      void *stream)
+{
+    if (!d_frames || !d_mask)
+        return fail(FIZI_EINVAL, "null frames or mask");
+    if (npx < 1)
+        return fail(FIZI_EINVAL, "npx must be >= 1");
+    if (reinterpret_cast<uintptr_t>(d_frames) % 4 != 0 || reinterpret_cast<uintptr_t>(d_mask) % 16 != 0)
+        return fail(FIZI_EINVAL, "frames must be 4-byte and the mask 16-byte aligned");
+    SoftParams s;
+    FIZI_TRY(soft_params(params6, T, &s));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    k_soft_fwd<<<soft_grid(npx), 256, 0, st>>>(d_frames, npx, s, d_mask);
+    FIZI_HIP(hipGetLastError());
+    return FIZI_OK;
+}
+
+size_t fizi_soft_workspace_bytes(int64_t npx)
+{
+    (void)npx;
+    return (size_t)kSoftBlocksMax * kSoftOut * sizeof(double);
+}
+
+int fizi_soft_backward(const uint8_t *d_frames, const float *d_dLdm, int64_t npx, const float params6[6], float T,
+                       void *d_workspace, size_t workspace_bytes, double *d_grad6, void *stream)
+{
+    if (!d_dLdm)
+        return fail(FIZI_EINVAL, "null dL/dm");
+    return soft_backward(d_frames, d_dLdm, nullptr, npx, params6, T, d_workspace, workspace_bytes, d_grad6, 6,
+                         stream);
+}
+
+int fizi_soft_bce(const uint8_t *d_frames, const uint8_t *d_gt, int64_t npx, const float params6[6], float T,
+                  void *d_workspace, size_t workspace_bytes, double *d_out7, void *stream)
+{
+    if (!d_gt)
+        return fail(FIZI_EINVAL, "null ground truth");
+    return soft_backward(d_frames, nullptr, d_gt, npx, params6, T, d_workspace, workspace_bytes, d_out7, 7,
+                         stream);
+}
+
+}  // extern "C"

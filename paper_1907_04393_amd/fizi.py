@@ -99,6 +99,11 @@ def _extra_signatures(L):
         L.fizi_batch_create.argtypes = [i32, P(Geom), P(Params), vp, ctypes.c_size_t, P(vp)]
         L.fizi_batch_learn.argtypes = [vp, i32, vp, i32, i32, vp]
         L.fizi_batch_step.argtypes = [vp, P(vp), P(vp), vp, vp]
+        L.fizi_batch_set_mode.argtypes = [vp, i32]
+        L.fizi_batch_status.argtypes = [vp, P(ctypes.c_uint32)]
+        L.fizi_batch_state_layout.argtypes = [vp, i32, P(Layout)]
+        L.fizi_batch_stage_timing.argtypes = [vp, i32]
+        L.fizi_batch_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
         L.fizi_batch_destroy.argtypes = [vp]
     if hasattr(L, "fizi_soft_forward"):
         L.fizi_soft_forward.argtypes = [vp, i64, P(ctypes.c_float), ctypes.c_float, vp, vp]
@@ -106,6 +111,8 @@ def _extra_signatures(L):
         L.fizi_soft_workspace_bytes.restype = ctypes.c_size_t
         L.fizi_soft_backward.argtypes = [vp, vp, i64, P(ctypes.c_float), ctypes.c_float, vp,
                                          ctypes.c_size_t, vp, vp]
+        L.fizi_soft_bce.argtypes = [vp, vp, i64, P(ctypes.c_float), ctypes.c_float, vp,
+                                    ctypes.c_size_t, vp, vp]
 
 
 def check(rc):
@@ -237,6 +244,102 @@ class Context:
     def close(self):
         if self._h:
             lib().fizi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+BATCH_DIRECT, BATCH_GRAPH, BATCH_PERSISTENT, BATCH_PERSISTENT_GRAPH = 0, 1, 2, 3
+
+
+class Batch:
+    """Many camera streams, one pipeline pass over all active ones per step."""
+
+    def __init__(self, geoms, params=None, device="cuda"):
+        L = lib()
+        self.n = len(geoms)
+        self.geoms = [(int(w), int(h)) for w, h in geoms]
+        if params is None or isinstance(params, Params):
+            params = [params or default_params()] * self.n
+        self.params = list(params)
+        self._g = (Geom * self.n)(*[Geom(w, h) for w, h in self.geoms])
+        self._p = (Params * self.n)(*self.params)
+        nbytes = int(L.fizi_batch_state_bytes(self.n, self._g, self._p))
+        if nbytes == 0:
+            raise FiziError(FIZI_EINVAL, "invalid stream geometry or parameters")
+        self.device = torch.device(device)
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        check(L.fizi_batch_create(self.n, self._g, self._p, _ptr(self.state), nbytes, ctypes.byref(self._h)))
+        self._frames = (ctypes.c_void_p * self.n)()
+        self._fizi = (ctypes.c_void_p * self.n)()
+
+    @staticmethod
+    def stream_bytes(geom, params=None) -> int:
+        """Device bytes one stream of this geometry adds to a batch (its
+        model and its frame scratch)."""
+        L = lib()
+        p = params or default_params()
+        g = Geom(int(geom[0]), int(geom[1]))
+        one = int(L.fizi_batch_state_bytes(1, (Geom * 1)(g), (Params * 1)(p)))
+        two = int(L.fizi_batch_state_bytes(2, (Geom * 2)(g, g), (Params * 2)(p, p)))
+        return two - one
+
+    def learn(self, stream_id, frames: torch.Tensor, reset=True, stream=None):
+        w, h = self.geoms[stream_id]
+        if frames.dtype != torch.uint8 or not frames.is_contiguous() or tuple(frames.shape[1:]) != (h, w, 3):
+            raise FiziError(FIZI_EINVAL, f"frames must be contiguous uint8 (n, {h}, {w}, 3)")
+        check(lib().fizi_batch_learn(self._h, int(stream_id), _ptr(frames), int(frames.shape[0]),
+                                     int(bool(reset)), _stream(stream)))
+
+    def step(self, frames, pointers: torch.Tensor, fizi=None, stream=None):
+        """frames: list of n device frames (H, W, 3) uint8 or None (idle);
+        pointers: (n, 56) uint8 device tensor; fizi: optional list of bit
+        tensors (entries may be None)."""
+        for i, f in enumerate(frames):
+            self._frames[i] = f.data_ptr() if f is not None else None
+        fz = None
+        if fizi is not None:
+            for i, f in enumerate(fizi):
+                self._fizi[i] = f.data_ptr() if f is not None else None
+            fz = self._fizi
+        check(lib().fizi_batch_step(self._h, self._frames, fz, _ptr(pointers), _stream(stream)))
+
+    def set_mode(self, mode: int):
+        check(lib().fizi_batch_set_mode(self._h, int(mode)))
+
+    def status(self) -> int:
+        f = ctypes.c_uint32()
+        check(lib().fizi_batch_status(self._h, ctypes.byref(f)))
+        return int(f.value)
+
+    def stage_timing(self, enable=True):
+        check(lib().fizi_batch_stage_timing(self._h, int(bool(enable))))
+
+    def stage_times(self) -> dict:
+        ms = (ctypes.c_double * 5)()
+        n = (ctypes.c_int64 * 5)()
+        check(lib().fizi_batch_stage_times(self._h, ms, n))
+        return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(Context.STAGES)}
+
+    def model(self, stream_id):
+        lay = Layout()
+        check(lib().fizi_batch_state_layout(self._h, int(stream_id), ctypes.byref(lay)))
+        w, h = self.geoms[stream_id]
+        px3 = w * h * 3
+        bgmin = self.state[lay.bgmin:lay.bgmin + px3].view(h, w, 3)
+        bgmax = self.state[lay.bgmax:lay.bgmax + px3].view(h, w, 3)
+        ny = int(lay.yref_rows) * w * 2
+        yref = self.state[lay.yref:lay.yref + ny].view(torch.int16).view(int(lay.yref_rows), w)
+        return bgmin, bgmax, yref
+
+    def close(self):
+        if self._h:
+            lib().fizi_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

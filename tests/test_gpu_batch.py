@@ -1,0 +1,157 @@
+"""GPU parity of the batched form: every stream's I_FIZI and pointer equal
+the CPU oracle's, in every launch mode (direct kernels, hipGraph replay,
+persistent fused kernel, persistent kernel from a hipGraph)."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+MODES = (0, 1, 2, 3)
+
+
+def _streams():
+    """Five streams of different sizes and thresholds."""
+    from paper_1907_04393_amd import scene
+    specs = [scene.SceneSpec(320, 240, sigma=3, seed=(5, 1, 0, 0)),
+             scene.SceneSpec(640, 480, sigma=4, seed=(5, 1, 0, 1), distractors=1),
+             scene.SceneSpec(128, 96, sigma=2, seed=(5, 1, 0, 2)),
+             scene.SceneSpec(192, 64, sigma=3, seed=(5, 1, 0, 3), gain="drift"),
+             scene.SceneSpec(64, 33, sigma=3, seed=(5, 1, 0, 4))]
+    params = [dict(), dict(), dict(open_iters=2, close_iters=0), dict(bg_delta=0, gray_S=5),
+              dict(alpha1_cdeg=30000, alpha2_cdeg=9000)]
+    data = []
+    for sp in specs:
+        sc = scene.Scene(sp)
+        data.append((sc.bg_frames(0, 8), sc.hand_frames(0, 6)))
+    return specs, params, data
+
+
+# which streams have a frame in each of the 6 steps
+ACTIVE = [[1, 1, 1, 1, 1], [1, 0, 1, 0, 1], [0, 1, 1, 1, 0], [1, 1, 0, 1, 1], [0, 0, 0, 0, 1],
+          [1, 1, 1, 1, 1]]
+
+
+def _oracle(specs, params, data):
+    from oracle import oracle
+    out = []
+    for sp, pr, (bg, hand) in zip(specs, params, data):
+        m = oracle.Model(sp.width, sp.height, oracle.params(**pr))
+        m.learn(bg.numpy())
+        out.append((m, hand))
+    return out
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_matches_oracle(mode):
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    specs, params, data = _streams()
+    print("batch mode", mode, flush=True)
+    b = fizi.Batch([(sp.width, sp.height) for sp in specs],
+                   [fizi.default_params(**p) for p in params], device=dev)
+    b.set_mode(mode)
+    for i, (bg, _) in enumerate(data):
+        b.learn(i, bg.to(dev))
+    hands = [h.to(dev) for _, h in data]
+    fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in specs]
+    orc = _oracle(specs, params, data)
+    counts = [0] * len(specs)
+    for k, act in enumerate(ACTIVE):
+        ptrs = torch.full((len(specs), 56), 0xAB, dtype=torch.uint8, device=dev)
+        frames = [hands[i][k] if act[i] else None for i in range(len(specs))]
+        b.step(frames, ptrs, fizi=fz)
+        torch.cuda.synchronize()
+        got = fizi.pointers_to_numpy(ptrs)
+        raw = ptrs.cpu().numpy()
+        for i, sp in enumerate(specs):
+            if not act[i]:
+                assert (raw[i] == 0xAB).all(), (k, i)
+                continue
+            m, hand = orc[i]
+            ref = m.process(hand[k].numpy(), frame_index=counts[i])
+            counts[i] += 1
+            assert fizi.pointer_dict(got[i]) == ref["pointer"], (mode, k, i)
+            assert np.array_equal(fizi.unpack_bits(fz[i], sp.width), ref["fizi"]), (mode, k, i)
+    assert b.status() == 0
+    b.close()
+
+
+def test_batch_learned_model_matches_oracle():
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    specs, params, data = _streams()
+    b = fizi.Batch([(sp.width, sp.height) for sp in specs],
+                   [fizi.default_params(**p) for p in params], device=dev)
+    for i, (bg, _) in enumerate(data):
+        b.learn(i, bg[:3].to(dev))
+        b.learn(i, bg[3:].to(dev), reset=False)
+    torch.cuda.synchronize()
+    for i, (m, _) in enumerate(_oracle(specs, params, data)):
+        bgmin, bgmax, yref = b.model(i)
+        assert np.array_equal(bgmin.cpu().numpy(), m.bgmin)
+        assert np.array_equal(bgmax.cpu().numpy(), m.bgmax)
+        assert np.array_equal(yref.cpu().numpy().view(np.uint16), m.yref)
+
+
+def test_batch_unlearned_stream_is_an_error():
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    b = fizi.Batch([(64, 8), (128, 8)], device=dev)
+    b.learn(0, torch.full((1, 8, 64, 3), 50, dtype=torch.uint8, device=dev))
+    ptrs = torch.zeros((2, 56), dtype=torch.uint8, device=dev)
+    with pytest.raises(fizi.FiziError) as e:
+        b.step([None, torch.zeros((8, 128, 3), dtype=torch.uint8, device=dev)], ptrs)
+    assert e.value.code == fizi.FIZI_ESTATE
+    b.step([None, None], ptrs)              # an empty step is a no-op
+    b.step([torch.full((8, 64, 3), 50, dtype=torch.uint8, device=dev), None], ptrs)
+    torch.cuda.synchronize()
+    p = fizi.pointer_dict(fizi.pointers_to_numpy(ptrs)[0])
+    assert p["present"] == 0 and p["frame_index"] == 0 and p["inv_gain_q16"] == 65536
+
+
+def test_batched_workload_full_size():
+    """The 64-stream workload at full size, in the benchmark's launch mode:
+    every stream's outputs equal the direct-launch mode's, and a sample of
+    streams equals the oracle."""
+    from oracle import oracle
+    from paper_1907_04393_amd import fizi, workloads
+    dev = need_gpu()
+    print("building 64-stream workload", flush=True)
+    w = workloads.batched(64, pool=2, device=dev, log=lambda m: print(m, flush=True))
+    b = w["batch"]
+    n = len(w["specs"])
+    res = {}
+    for mode in (workloads.BATCH_MODE, fizi.BATCH_DIRECT):
+        b.set_mode(mode)
+        outs = []
+        for k in range(2):
+            ptrs = torch.empty((n, 56), dtype=torch.uint8, device=dev)
+            fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in w["specs"]]
+            b.step(workloads.step_frames(w, k), ptrs, fizi=fz)
+            torch.cuda.synchronize()
+            outs.append((fizi.pointers_to_numpy(ptrs).copy(), [f.cpu().numpy() for f in fz]))
+        res[mode] = outs
+        assert b.status() == 0
+    for k in range(2):
+        a, d = res[workloads.BATCH_MODE][k], res[fizi.BATCH_DIRECT][k]
+        for i in range(n):
+            ga, gd = fizi.pointer_dict(a[0][i]), fizi.pointer_dict(d[0][i])
+            gd["frame_index"] = ga["frame_index"]
+            assert ga == gd, (k, i)
+            assert np.array_equal(a[1][i], d[1][i]), (k, i)
+    rng = np.random.default_rng(0)
+    sample = sorted(rng.choice(n, size=6, replace=False).tolist())
+    print("oracle sample", sample, flush=True)
+    for i in sample:
+        sp, sc = w["specs"][i], w["scenes"][i]
+        m = oracle.Model(sp.width, sp.height)
+        m.learn(sc.bg_frames(0, 30).cpu().numpy())
+        for k in range(2):
+            ref = m.process(w["frames"][i][k].cpu().numpy(), frame_index=k)
+            got = fizi.pointer_dict(res[workloads.BATCH_MODE][k][0][i])
+            assert got == ref["pointer"], (i, k)
+            bits = res[workloads.BATCH_MODE][k][1][i]
+            assert np.array_equal(fizi.unpack_bits(torch.from_numpy(bits), sp.width), ref["fizi"]), (i, k)

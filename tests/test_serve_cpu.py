@@ -1,0 +1,151 @@
+"""The serving loop's scheduling on a CPU backend that runs the oracle:
+every frame is served exactly once, in order per stream, with the result it
+has alone; a tight memory budget defers admissions without dropping frames;
+slots are reused."""
+import collections
+
+import numpy as np
+import pytest
+
+from paper_1907_04393_amd import serve
+
+
+class OracleBackend:
+    """Slots over the CPU oracle; a step finishes `delay` seconds later."""
+
+    def __init__(self, slot_geoms, lanes=2, delay=0.002, clock=None):
+        from oracle import oracle
+        self.O = oracle
+        self.slot_geom = list(slot_geoms)
+        self.n_lanes = lanes
+        self.free = collections.defaultdict(list)
+        for i, g in enumerate(self.slot_geom):
+            self.free[g].append(i)
+        self.models = {}
+        self.delay = delay
+        self.clock = clock
+        self.steps = []
+        self.live = set()
+
+    def lanes(self):
+        return range(self.n_lanes)
+
+    def lane_of(self, slot):
+        return slot % self.n_lanes
+
+    def acquire(self, w, h):
+        f = self.free.get((w, h))
+        if not f:
+            return None
+        s = f.pop()
+        assert s not in self.live
+        self.live.add(s)
+        return s
+
+    def release(self, slot):
+        self.live.discard(slot)
+        self.models.pop(slot, None)
+        self.free[self.slot_geom[slot]].append(slot)
+
+    def learn(self, slot, frames, params=None):
+        w, h = self.slot_geom[slot]
+        m = self.O.Model(w, h)
+        m.learn(np.asarray(frames))
+        self.models[slot] = m
+
+    def step(self, lane, frames):
+        out = {}
+        for slot, f in frames.items():
+            assert self.lane_of(slot) == lane and slot in self.live
+            out[slot] = self.models[slot].process(np.asarray(f))["pointer"]
+        self.steps.append(len(frames))
+        import time
+        return (time.perf_counter() + self.delay, out)
+
+    def done(self, h):
+        import time
+        return time.perf_counter() >= h[0]
+
+    def pointers(self, h):
+        return h[1]
+
+
+def _sessions(n, dur, rate=30.0, seed=0, sizes=((64, 24), (128, 16)), session_len=None):
+    from paper_1907_04393_amd import scene
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        w, h = sizes[i % len(sizes)]
+        sc = scene.Scene(scene.SceneSpec(w, h, sigma=2, n_hand=8, seed=(9, seed, i, 0)))
+        bg = sc.bg_frames(0, 4).numpy()
+        pool = sc.hand_frames(0, 4).numpy()
+        start = 0.0 if session_len is None else float(rng.uniform(0, dur * 0.5))
+        end = dur if session_len is None else min(dur, start + session_len)
+        arr = serve.poisson_arrivals(rate, start + 0.01, end, rng)
+        out.append(serve.Session(i, w, h, bg, (lambda k, p=pool: p[k % 4]), arr, start=start))
+    return out
+
+
+def _check_alone(sessions, results):
+    """Each result equals that frame processed alone by a fresh oracle."""
+    from oracle import oracle
+    by = {s.sid: s for s in sessions}
+    models = {}
+    for r in results:
+        s = by[r.sid]
+        if r.sid not in models:
+            models[r.sid] = oracle.Model(s.width, s.height)
+            models[r.sid].learn(s.bg)
+        ref = models[r.sid].process(s.frames(r.seq))["pointer"]
+        got = dict(r.pointer)
+        got["frame_index"] = ref["frame_index"]
+        assert got == ref, (r.sid, r.seq)
+
+
+def test_every_frame_served_once_in_order():
+    sessions = _sessions(6, 0.6)
+    be = OracleBackend([(64, 24)] * 3 + [(128, 16)] * 3)
+    srv = serve.Server(be)
+    res = srv.run(sessions, 0.6)
+    want = {(s.sid, k) for s in sessions for k in range(len(s.arrivals))}
+    got = [(r.sid, r.seq) for r in res]
+    assert len(got) == len(set(got)) and set(got) == want
+    for sid in range(6):
+        seqs = [r.seq for r in res if r.sid == sid]
+        assert seqs == sorted(seqs)
+    assert all(r.latency >= 0 for r in res)
+    assert not srv.deferred
+    _check_alone(sessions, res)
+    assert max(be.steps) > 1            # frames of several streams share steps
+
+
+def test_tight_budget_defers_without_dropping():
+    """Two slots per class for eight sessions that come and go: admissions
+    wait for slots, slots are reused, no frame is lost."""
+    sessions = _sessions(8, 1.0, session_len=0.25, seed=3)
+    be = OracleBackend([(64, 24)] * 2 + [(128, 16)] * 2)
+    srv = serve.Server(be)
+    res = srv.run(sessions, 1.0)
+    want = {(s.sid, k) for s in sessions for k in range(len(s.arrivals))}
+    assert {(r.sid, r.seq) for r in res} == want
+    assert srv.deferred              # some sessions had to wait
+    _check_alone(sessions, res)
+    assert not be.live                # every slot released at the end
+
+
+def test_plan_slots():
+    classes = [(640, 480), (1280, 720), (1920, 1080), (3840, 2160)]
+    size = {c: c[0] * c[1] * 20 for c in classes}
+    demand = {classes[0]: 10, classes[1]: 10, classes[2]: 10, classes[3]: 10}
+    full = serve.plan_slots(classes, demand, size, 10 ** 12)
+    assert full == demand
+    tight = serve.plan_slots(classes, demand, size, 600_000_000)
+    assert sum(tight[c] * size[c] for c in classes) <= 600_000_000
+    assert all(tight[c] >= 1 for c in classes)
+    assert all(tight[c] <= demand[c] for c in classes)
+
+
+def test_poisson_rate():
+    rng = np.random.default_rng(0)
+    a = serve.poisson_arrivals(30.0, 0.0, 200.0, rng)
+    assert abs(len(a) / 200.0 - 30.0) < 1.5 and all(np.diff(a) > 0)
