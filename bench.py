@@ -132,6 +132,26 @@ def bench_plain(args, torch, fizi, scene):
                            "mode": "one frame per call, pointer read back on the host"}}
 
 
+def bench_serving(args, torch, workloads, budget=None, session_len=None, duration=None):
+    from paper_1907_04393_amd import serve
+    duration = duration or args.serve_seconds
+    sessions, be, admitted, px_of, plan, size = workloads.serving(
+        256, duration=duration, budget=budget, session_len=session_len, log=log)
+    srv = serve.Server(be)
+    t0 = time.perf_counter()
+    res = srv.run(sessions, duration, admitted=admitted)
+    wall = time.perf_counter() - t0
+    out = serve.summarize(res, px_of, wall)
+    out.update({"streams": len(sessions), "seconds": duration,
+                "offered_frames": sum(len(s.arrivals) for s in sessions),
+                "steps": srv.steps, "slots": {f"{c[0]}x{c[1]}": n for c, n in plan.items()},
+                "state_GB": round(sum(plan[c] * size[c] for c in plan) / 1e9, 2),
+                "deferred_sessions": len(srv.deferred)})
+    be.close()
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_baseline(args, fizi, w):
     """The oracle on a sample of the batched workload's frames (learning of
     the sampled streams' models is set-up, not timed)."""
@@ -170,6 +190,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (the pipeline has no multi-GPU path); "
@@ -186,6 +208,13 @@ def main():
     plain = None if args.no_plain else bench_plain(args, torch, fizi, scene)
     if plain:
         log("plain:", plain)
+    serving = None
+    if not args.no_serve:
+        serving = {"budget_all_resident": bench_serving(args, torch, workloads)}
+        log("serving:", serving["budget_all_resident"])
+        serving["budget_4GB_sessions_come_and_go"] = bench_serving(
+            args, torch, workloads, budget=4e9, session_len=2.0, duration=min(6.0, args.serve_seconds))
+        log("serving tight:", serving["budget_4GB_sessions_come_and_go"])
     cpu = None if args.no_cpu else cpu_baseline(args, fizi, r["w"])
     if cpu:
         log("cpu:", cpu)
@@ -215,6 +244,7 @@ def main():
                      "avg_launch_us": round(r["k_avg"] * 1e6, 2),
                      "bytes_per_launch": int(PATH_BYTES_PER_PX * r["px"])},
         "plain_single_stream": plain,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

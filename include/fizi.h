@@ -237,6 +237,31 @@ int fizi_batch_state_layout(fizi_batch *b, int32_t stream_id, fizi_layout *out);
 int fizi_batch_stage_timing(fizi_batch *b, int32_t enable);
 int fizi_batch_stage_times(fizi_batch *b, double *h_ms, int64_t *h_launches);
 
+/* Launch shapes of a batch. cls_iters: classify tile = 1024 * cls_iters
+ * pixels (1, 2, 4, 8; the persistent kernel uses 2, 4 or 8); morph_rows:
+ * morphology band height (8, 16, 32, 64, within 64 KiB of LDS for the widest
+ * stream); grid_per_cu: resident blocks per CU for the streaming kernels
+ * (1..32); mode: FIZI_BATCH_*. Results do not depend on them. */
+typedef struct {
+    int32_t cls_iters;
+    int32_t morph_rows;
+    int32_t grid_per_cu;
+    int32_t mode;
+} fizi_tuning;
+
+int fizi_batch_get_tuning(fizi_batch *b, fizi_tuning *out);
+/* Waits for pending steps; FIZI_EINVAL for a shape outside the ranges. */
+int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t);
+
+/* Autotuner (the paper's Section 3.3 tunes its GPU memory use dynamically;
+ * here the launch shapes are tuned on the caller's workload): times `steps`
+ * frame steps of h_frames (as in fizi_batch_step, after two warm-up steps)
+ * for each candidate of a coordinate sweep - mode, then cls_iters, then
+ * grid_per_cu, then morph_rows - keeps the fastest, leaves it set, and
+ * returns it with its milliseconds per step. Synchronous. */
+int fizi_batch_autotune(fizi_batch *b, const uint8_t *const *h_frames, fizi_pointer *d_pointers,
+                        int32_t steps, void *stream, fizi_tuning *best, double *best_ms);
+
 /* Waits for the batch's work and releases its host resources. */
 int fizi_batch_destroy(fizi_batch *b);
 

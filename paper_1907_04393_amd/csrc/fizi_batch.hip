@@ -1,6 +1,7 @@
 // C ABI of the batched form: many camera streams of uneven resolution, one
 // pipeline pass over all of them per frame step (include/fizi.h).
 #include <algorithm>
+#include <initializer_list>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -269,6 +270,116 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
     }
     FIZI_TRY(b->ring.finish(slot, s));
     return mark_last(b, s);
+}
+
+int fizi_batch_get_tuning(fizi_batch *b, fizi_tuning *out)
+{
+    if (!b || !out)
+        return fail(FIZI_EINVAL, "null argument");
+    out->cls_iters = b->tune.cls_iters;
+    out->morph_rows = b->tune.morph_rows;
+    out->grid_per_cu = b->tune.grid_per_cu;
+    out->mode = b->mode;
+    return FIZI_OK;
+}
+
+int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t)
+{
+    if (!b || !t)
+        return fail(FIZI_EINVAL, "null argument");
+    const bool persistent = t->mode == FIZI_BATCH_PERSISTENT || t->mode == FIZI_BATCH_PERSISTENT_GRAPH;
+    if (t->cls_iters != 1 && t->cls_iters != 2 && t->cls_iters != 4 && t->cls_iters != 8)
+        return fail(FIZI_EINVAL, "cls_iters must be 1, 2, 4 or 8");
+    if (persistent && t->cls_iters == 1)
+        return fail(FIZI_EINVAL, "the persistent kernel takes cls_iters 2, 4 or 8");
+    if (t->morph_rows != 8 && t->morph_rows != 16 && t->morph_rows != 32 && t->morph_rows != 64)
+        return fail(FIZI_EINVAL, "morph_rows must be 8, 16, 32 or 64");
+    if (2ull * (t->morph_rows + 2 * b->max_ops) * b->max_wd * 8 > kLdsBudget)
+        return fail(FIZI_EINVAL, "morph_rows too large for the LDS budget at this width");
+    if (t->grid_per_cu < 1 || t->grid_per_cu > 32)
+        return fail(FIZI_EINVAL, "grid_per_cu must be in [1, 32]");
+    if (t->mode < FIZI_BATCH_DIRECT || t->mode > FIZI_BATCH_PERSISTENT_GRAPH)
+        return fail(FIZI_EINVAL, "unknown batch mode");
+    if (b->have_last)
+        FIZI_HIP(hipEventSynchronize(b->order_ev));
+    drop_graphs(b);
+    b->tune.cls_iters = t->cls_iters;
+    b->tune.morph_rows = t->morph_rows;
+    b->tune.grid_per_cu = t->grid_per_cu;
+    b->mode = t->mode;
+    return FIZI_OK;
+}
+
+int fizi_batch_autotune(fizi_batch *b, const uint8_t *const *h_frames, fizi_pointer *d_pointers, int32_t steps,
+                        void *stream, fizi_tuning *best, double *best_ms)
+{
+    if (!b || !h_frames || !d_pointers || !best || !best_ms)
+        return fail(FIZI_EINVAL, "null argument");
+    if (steps < 1)
+        return fail(FIZI_EINVAL, "steps must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    FIZI_HIP(hipEventCreate(&e0));
+    FIZI_HIP(hipEventCreate(&e1));
+    // ms per step of a candidate, or +inf when it is not valid here
+    auto measure = [&](const fizi_tuning &t, double *ms) -> int {
+        *ms = 1e30;
+        if (fizi_batch_set_tuning(b, &t) != FIZI_OK)
+            return FIZI_OK;
+        for (int i = 0; i < 2; ++i)
+            FIZI_TRY(fizi_batch_step(b, h_frames, nullptr, d_pointers, stream));
+        FIZI_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < steps; ++i)
+            FIZI_TRY(fizi_batch_step(b, h_frames, nullptr, d_pointers, stream));
+        FIZI_HIP(hipEventRecord(e1, s));
+        FIZI_HIP(hipEventSynchronize(e1));
+        float el = 0.f;
+        FIZI_HIP(hipEventElapsedTime(&el, e0, e1));
+        uint32_t flags = 0;
+        FIZI_TRY(fizi_batch_status(b, &flags));
+        if (flags == 0)
+            *ms = el / steps;
+        return FIZI_OK;
+    };
+    fizi_tuning cur;
+    FIZI_TRY(fizi_batch_get_tuning(b, &cur));
+    if (cur.cls_iters == 1)
+        cur.cls_iters = 4;
+    double cur_ms;
+    int rc = measure(cur, &cur_ms);
+    auto sweep = [&](int32_t fizi_tuning::*field, std::initializer_list<int> values) -> int {
+        fizi_tuning base = cur;
+        for (int v : values) {
+            fizi_tuning t = base;
+            t.*field = v;
+            if (v == base.*field)
+                continue;
+            double ms;
+            FIZI_TRY(measure(t, &ms));
+            if (ms < cur_ms) {
+                cur_ms = ms;
+                cur = t;
+            }
+        }
+        return FIZI_OK;
+    };
+    if (rc == FIZI_OK)
+        rc = sweep(&fizi_tuning::mode, {FIZI_BATCH_GRAPH, FIZI_BATCH_PERSISTENT_GRAPH});
+    if (rc == FIZI_OK)
+        rc = sweep(&fizi_tuning::cls_iters, {2, 4, 8});
+    if (rc == FIZI_OK)
+        rc = sweep(&fizi_tuning::grid_per_cu, {4, 8, 16});
+    if (rc == FIZI_OK)
+        rc = sweep(&fizi_tuning::morph_rows, {8, 16, 32, 64});
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    FIZI_TRY(rc);
+    if (cur_ms >= 1e29)
+        return fail(FIZI_EHIP, "no launch shape completed without error");
+    FIZI_TRY(fizi_batch_set_tuning(b, &cur));
+    *best = cur;
+    *best_ms = cur_ms;
+    return FIZI_OK;
 }
 
 int fizi_batch_status(fizi_batch *b, uint32_t *h_flags)

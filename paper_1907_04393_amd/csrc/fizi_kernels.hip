@@ -72,10 +72,11 @@ __device__ __forceinline__ int find_job(const int32_t *pre, int nj, int t)
 }
 
 // Brightness correction of one channel value (Q16 inverse gain, half up,
-// saturated).
+// saturated). v < 2^8 and inv <= 2^20 both fit 24 bits, so the full-rate
+// 24-bit multiply gives the exact product (< 2^28).
 __device__ __forceinline__ uint32_t corr(uint32_t v, uint32_t inv)
 {
-    uint32_t t = (v * inv + 32768u) >> 16;
+    uint32_t t = (__umul24(v, inv) + 32768u) >> 16;
     return t < 255u ? t : 255u;
 }
 
@@ -96,17 +97,20 @@ __device__ __forceinline__ uint32_t inv_gain(unsigned long long num, unsigned lo
 
 // Skin-hue membership without division; see HueTest. Chroma > 0 is checked
 // by the caller.
+// Every factor fits the full-rate 24-bit signed multiply: |k| <= 6000,
+// |R - B| <= 255, d <= 6000, sum(d) <= 12000, R + G + B <= 765.
 __device__ __forceinline__ bool hue_in(int r, int g, int b, const HueTest &h)
 {
     const int rb = r - b, gb = g - b;
-    const int d1 = h.k1r * rb + h.k1g * gb;
+    const int d1 = __mul24(h.k1r, rb) + __mul24(h.k1g, gb);
     if (h.mode == 1)
-        return (d1 >= 0) & (h.k2r * rb + h.k2g * gb <= 0);
+        return (d1 >= 0) & (__mul24(h.k2r, rb) + __mul24(h.k2g, gb) <= 0);
     if (h.mode == 3)
-        return (d1 >= 0) | (h.k2r * rb + h.k2g * gb <= 0);
+        return (d1 >= 0) | (__mul24(h.k2r, rb) + __mul24(h.k2g, gb) <= 0);
     if (h.mode == 2)
         return d1 >= 0;
-    return (d1 == 0) & (3 * (h.dr * r + h.dg * g + h.db * b) - h.dsum * (r + g + b) > 0);
+    const int dp = __mul24(h.dr, r) + __mul24(h.dg, g) + __mul24(h.db, b);
+    return (d1 == 0) & (3 * dp - __mul24(h.dsum, r + g + b) > 0);
 }
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t w0, uint32_t w1, uint32_t w2, int i)
@@ -999,12 +1003,19 @@ hipError_t launch_persistent(const Table *d_tab, int max_wd, int max_ops, int n_
     const uint32_t lds = (uint32_t)(2 * (size_t)buf_words * sizeof(uint64_t));
     Table *tab = const_cast<Table *>(d_tab);
     PersistState *ps = reinterpret_cast<PersistState *>(persist);
-    switch (t.morph_rows) {
-    case 8: return launch_step_t<4, 8>(tab, buf_words, lds, n_cu, ps, s, ev);
-    case 16: return launch_step_t<4, 16>(tab, buf_words, lds, n_cu, ps, s, ev);
-    case 64: return launch_step_t<4, 64>(tab, buf_words, lds, n_cu, ps, s, ev);
-    default: return launch_step_t<4, 32>(tab, buf_words, lds, n_cu, ps, s, ev);
+#define FIZI_STEP_R(IT)                                                               \
+    switch (t.morph_rows) {                                                           \
+    case 8: return launch_step_t<IT, 8>(tab, buf_words, lds, n_cu, ps, s, ev);        \
+    case 16: return launch_step_t<IT, 16>(tab, buf_words, lds, n_cu, ps, s, ev);      \
+    case 64: return launch_step_t<IT, 64>(tab, buf_words, lds, n_cu, ps, s, ev);      \
+    default: return launch_step_t<IT, 32>(tab, buf_words, lds, n_cu, ps, s, ev);      \
     }
+    switch (t.cls_iters) {
+    case 2: FIZI_STEP_R(2)
+    case 8: FIZI_STEP_R(8)
+    default: FIZI_STEP_R(4)
+    }
+#undef FIZI_STEP_R
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s)

@@ -42,6 +42,14 @@ class PointerC(ctypes.Structure):
                 ("frame_index", ctypes.c_uint64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("cls_iters", ctypes.c_int32), ("morph_rows", ctypes.c_int32),
+                ("grid_per_cu", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class Layout(ctypes.Structure):
     _fields_ = [("bgmin", ctypes.c_uint64), ("bgmax", ctypes.c_uint64), ("yref", ctypes.c_uint64),
                 ("yref_rows", ctypes.c_uint64), ("total", ctypes.c_uint64)]
@@ -105,6 +113,9 @@ def _extra_signatures(L):
         L.fizi_batch_stage_timing.argtypes = [vp, i32]
         L.fizi_batch_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
         L.fizi_batch_destroy.argtypes = [vp]
+        L.fizi_batch_get_tuning.argtypes = [vp, P(Tuning)]
+        L.fizi_batch_set_tuning.argtypes = [vp, P(Tuning)]
+        L.fizi_batch_autotune.argtypes = [vp, P(vp), vp, i32, vp, P(Tuning), P(ctypes.c_double)]
     if hasattr(L, "fizi_soft_forward"):
         L.fizi_soft_forward.argtypes = [vp, i64, P(ctypes.c_float), ctypes.c_float, vp, vp]
         L.fizi_soft_workspace_bytes.argtypes = [i64]
@@ -308,6 +319,25 @@ class Batch:
                 self._fizi[i] = f.data_ptr() if f is not None else None
             fz = self._fizi
         check(lib().fizi_batch_step(self._h, self._frames, fz, _ptr(pointers), _stream(stream)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        check(lib().fizi_batch_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{**self.get_tuning(), **kw})
+        check(lib().fizi_batch_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, frames, pointers, steps=5, stream=None):
+        """Times candidate launch shapes on these frames; keeps the fastest.
+        Returns (tuning dict, ms per step)."""
+        for i, f in enumerate(frames):
+            self._frames[i] = f.data_ptr() if f is not None else None
+        t, ms = Tuning(), ctypes.c_double()
+        check(lib().fizi_batch_autotune(self._h, self._frames, _ptr(pointers), int(steps), _stream(stream),
+                                        ctypes.byref(t), ctypes.byref(ms)))
+        return t.as_dict(), float(ms.value)
 
     def set_mode(self, mode: int):
         check(lib().fizi_batch_set_mode(self._h, int(mode)))

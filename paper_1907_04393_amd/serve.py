@@ -108,16 +108,20 @@ class Server:
         self.steps = 0
         self.max_queue = 0
 
-    def run(self, sessions, duration, t_max=None):
+    def run(self, sessions, duration, t_max=None, admitted=None):
         """Serves the sessions' frames that arrive before `duration` seconds,
-        then drains the queues. Returns the list of FrameResult."""
+        then drains the queues. `admitted` maps sessions already bound (and
+        learned) before the run to their slots. Returns the FrameResults."""
         be = self.be
+        if hasattr(be, "begin"):
+            be.begin()
         t0 = self.clock()
         now = lambda: self.clock() - t0                        # noqa: E731
         by_sid = {s.sid: s for s in sessions}
-        pending = sorted(sessions, key=lambda s: s.start)       # not yet asking
+        admitted = dict(admitted or {})
+        pending = sorted((s for s in sessions if s.sid not in admitted), key=lambda s: s.start)
         waiting = collections.deque()                          # asking, no slot yet
-        bound = {}                                             # sid -> slot
+        bound = dict(admitted)                                 # sid -> slot
         queues = {s.sid: collections.deque() for s in sessions}
         nxt = {s.sid: 0 for s in sessions}
         heap = [(s.arrivals[0], s.sid) for s in sessions if s.arrivals and s.arrivals[0] < duration]
@@ -252,12 +256,19 @@ class GpuBackend:
     def release(self, slot):
         self.free[self.slot_geom[slot]].append(slot)
 
+    def begin(self):
+        """Frames made on other streams before the run are complete."""
+        self.torch.cuda.synchronize()
+
     def learn(self, slot, frames, params=None):
         L = self.lane_of(slot)
         j = self.lane_slots[L].index(slot)
         s = self.streams[L]
-        with self.torch.cuda.stream(s):
-            self.batches[L].learn(j, frames, reset=True, stream=s)
+        # the frames come from the current stream; the lane reads them, and the
+        # allocator must not hand their memory out before the lane is done
+        s.wait_stream(self.torch.cuda.current_stream())
+        frames.record_stream(s)
+        self.batches[L].learn(j, frames, reset=True, stream=s)
 
     def step(self, lane, frames):
         torch = self.torch

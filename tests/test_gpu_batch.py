@@ -155,3 +155,65 @@ def test_batched_workload_full_size():
             assert got == ref["pointer"], (i, k)
             bits = res[workloads.BATCH_MODE][k][1][i]
             assert np.array_equal(fizi.unpack_bits(torch.from_numpy(bits), sp.width), ref["fizi"]), (i, k)
+
+
+def _run_steps(b, hands, specs, nsteps, dev):
+    from paper_1907_04393_amd import fizi
+    outs = []
+    for k in range(nsteps):
+        ptrs = torch.empty((len(specs), 56), dtype=torch.uint8, device=dev)
+        fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in specs]
+        b.step([h[k] for h in hands], ptrs, fizi=fz)
+        torch.cuda.synchronize()
+        ps = [fizi.pointer_dict(p) for p in fizi.pointers_to_numpy(ptrs)]
+        for p in ps:
+            p.pop("frame_index")
+        outs.append((ps, [f.cpu().numpy() for f in fz]))
+    assert b.status() == 0
+    return outs
+
+
+def _same(a, b):
+    for (pa, fa), (pb, fb) in zip(a, b):
+        assert pa == pb
+        assert all(np.array_equal(x, y) for x, y in zip(fa, fb))
+
+
+def test_every_launch_shape_gives_the_same_result():
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    specs, params, data = _streams()
+    b = fizi.Batch([(sp.width, sp.height) for sp in specs],
+                   [fizi.default_params(**p) for p in params], device=dev)
+    for i, (bg, _) in enumerate(data):
+        b.learn(i, bg.to(dev))
+    hands = [h.to(dev) for _, h in data]
+    b.set_tuning(mode=0, cls_iters=4, morph_rows=32, grid_per_cu=8)
+    ref = _run_steps(b, hands, specs, 2, dev)
+    shapes = [dict(mode=m, cls_iters=c, morph_rows=r, grid_per_cu=g)
+              for m in (0, 1, 2, 3) for c in (2, 8) for r in (8, 64) for g in ((1, 16) if m == 0 else (8,))]
+    shapes += [dict(mode=0, cls_iters=1, morph_rows=16, grid_per_cu=4)]
+    for sh in shapes:
+        print("shape", sh, flush=True)
+        b.set_tuning(**sh)
+        assert b.get_tuning() == sh
+        _same(_run_steps(b, hands, specs, 2, dev), ref)
+
+
+def test_autotune_keeps_results():
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    specs, params, data = _streams()
+    b = fizi.Batch([(sp.width, sp.height) for sp in specs],
+                   [fizi.default_params(**p) for p in params], device=dev)
+    for i, (bg, _) in enumerate(data):
+        b.learn(i, bg.to(dev))
+    hands = [h.to(dev) for _, h in data]
+    ref = _run_steps(b, hands, specs, 2, dev)
+    ptrs = torch.empty((len(specs), 56), dtype=torch.uint8, device=dev)
+    best, ms = b.autotune([h[0] for h in hands], ptrs, steps=3)
+    print("autotuned", best, ms, flush=True)
+    assert ms > 0 and best == b.get_tuning()
+    _same(_run_steps(b, hands, specs, 2, dev), ref)
+    with pytest.raises(fizi.FiziError):
+        b.set_tuning(cls_iters=3)
