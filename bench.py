@@ -152,6 +152,62 @@ def bench_serving(args, torch, workloads, budget=None, session_len=None, duratio
     return out
 
 
+def bench_learn(args, torch, fizi, scene):
+    """Background learning, 50 frames of 1920x1080: every frame is read once
+    (3 B/px), the model is read and written once (12 B/px per call)."""
+    dev = torch.device("cuda:0")
+    spec = scene.hd_plain()
+    W, H, n = spec.width, spec.height, spec.n_bg
+    bg = scene.Scene(spec, device=dev).bg_frames(0, n)
+    ctx = fizi.Context(W, H, chunk=1, device=dev)
+    ctx.learn_background(bg)
+    torch.cuda.synchronize()
+    ctx.stage_timing(True)
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.learn_background(bg)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    ms, launches = ctx.stage_times()["learn"]
+    k_s = ms / 1e3 / max(1, launches)
+    byts = W * H * (3 * n + 12)
+    return {"workload": f"{n} frames 1920x1080 per call", "ms_per_call": round(sec * 1e3, 3),
+            "frames_per_s": round(n / sec, 1), "minmax_kernel_us": round(k_s * 1e6, 1),
+            "minmax_GBps": round(byts / k_s / 1e9, 1), "minmax_frac": round(byts / k_s / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def bench_soft(args, torch, scene):
+    """Soft mask on the calibration workload (32 frames 1280x720): forward
+    (3 B in, 4 B out per px), backward from dL/dm (3 + 4 B in), fused BCE
+    loss and gradient (3 + 1 B in)."""
+    from paper_1907_04393_amd import soft
+    dev = torch.device("cuda:0")
+    f, gt = scene.Scene(scene.calibration(), device=dev).hand_frames(0, 32, with_gt=True)
+    gt = gt.to(torch.uint8)
+    npx = f.numel() // 3
+    prm = torch.tensor((102.0, 153.0, 208.3, 10.0, 133.3, 2.5), dtype=torch.float64)
+    m = soft.soft_forward(f, prm, 0.5)
+    dm = torch.randn_like(m)
+    soft.soft_backward(f, dm, prm, 0.5)
+    torch.cuda.synchronize()
+    reps = 20
+    out = {"workload": "32 frames 1280x720 (29.5 Mpx), T = 0.5"}
+    for name, fn, bpp in (("forward", lambda: soft.soft_forward(f, prm, 0.5, out=m), 7),
+                          ("backward", lambda: soft.soft_backward(f, dm, prm, 0.5), 7),
+                          ("fused_bce", lambda: soft.soft_bce(f, gt, prm, 0.5), 4)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        out[name] = {"us": round(sec * 1e6, 1), "GBps": round(npx * bpp / sec / 1e9, 1),
+                     "frac": round(npx * bpp / sec / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def cpu_baseline(args, fizi, w):
     """The oracle on a sample of the batched workload's frames (learning of
     the sampled streams' models is set-up, not timed)."""
@@ -192,6 +248,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device to device 3 times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (the pipeline has no multi-GPU path); "
@@ -201,13 +259,24 @@ def main():
     import torch
     from paper_1907_04393_amd import fizi, scene, workloads
 
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
     r = bench_batched(args, torch, fizi, workloads)
     mpxs = r["px"] / r["sec"] / 1e6
     fps = r["n"] / r["sec"]
     log(f"batched: {mpxs:.0f} Mpx/s, {fps:.0f} frames/s, {r['sec'] * 1e3:.3f} ms/step")
     plain = None if args.no_plain else bench_plain(args, torch, fizi, scene)
     if plain:
+        plain["learn_background"] = bench_learn(args, torch, fizi, scene)
         log("plain:", plain)
+    soft_res = None if args.no_plain else bench_soft(args, torch, scene)
+    if soft_res:
+        log("soft:", soft_res)
     serving = None
     if not args.no_serve:
         serving = {"budget_all_resident": bench_serving(args, torch, workloads)}
@@ -245,6 +314,7 @@ def main():
                      "bytes_per_launch": int(PATH_BYTES_PER_PX * r["px"])},
         "plain_single_stream": plain,
         "serving": serving,
+        "soft_mask": soft_res,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -239,8 +239,8 @@ int fizi_batch_stage_times(fizi_batch *b, double *h_ms, int64_t *h_launches);
 
 /* Launch shapes of a batch. cls_iters: classify tile = 1024 * cls_iters
  * pixels (1, 2, 4, 8; the persistent kernel uses 2, 4 or 8); morph_rows:
- * morphology band height (8, 16, 32, 64, within 64 KiB of LDS for the widest
- * stream); grid_per_cu: resident blocks per CU for the streaming kernels
+ * morphology band height (8, 16, 32, 64); grid_per_cu: resident blocks per
+ * CU for the streaming kernels
  * (1..32); mode: FIZI_BATCH_*. Results do not depend on them. */
 typedef struct {
     int32_t cls_iters;

@@ -294,8 +294,6 @@ int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t)
         return fail(FIZI_EINVAL, "the persistent kernel takes cls_iters 2, 4 or 8");
     if (t->morph_rows != 8 && t->morph_rows != 16 && t->morph_rows != 32 && t->morph_rows != 64)
         return fail(FIZI_EINVAL, "morph_rows must be 8, 16, 32 or 64");
-    if (2ull * (t->morph_rows + 2 * b->max_ops) * b->max_wd * 8 > kLdsBudget)
-        return fail(FIZI_EINVAL, "morph_rows too large for the LDS budget at this width");
     if (t->grid_per_cu < 1 || t->grid_per_cu > 32)
         return fail(FIZI_EINVAL, "grid_per_cu must be in [1, 32]");
     if (t->mode < FIZI_BATCH_DIRECT || t->mode > FIZI_BATCH_PERSISTENT_GRAPH)

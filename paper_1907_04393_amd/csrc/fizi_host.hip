@@ -99,14 +99,12 @@ int morph_ops(const fizi_params &p) { return 2 * (p.open_iters + p.close_iters);
 
 Tuning tuning_for(int max_width, int max_ops)
 {
+    (void)max_width;
+    (void)max_ops;
     Tuning t;
     t.cls_iters = 4;
     t.grid_per_cu = 8;
-    const int wd = max_width / 64;
-    int R = 32;
-    while (R > 8 && 2ull * (R + 2 * max_ops) * wd * 8 > kLdsBudget)
-        R /= 2;
-    t.morph_rows = R;
+    t.morph_rows = 16;
     return t;
 }
 
@@ -194,7 +192,8 @@ void set_prefixes(Table &T, int njobs, const Tuning &t)
     for (int i = 0; i < njobs; ++i) {
         const Job &J = T.jobs[i];
         const long px = (long)J.W * J.H;
-        T.h.gain_pre[i + 1] = T.h.gain_pre[i] + (J.H + J.rs - 1) / J.rs;
+        const int rows = (J.H + J.rs - 1) / J.rs;
+        T.h.gain_pre[i + 1] = T.h.gain_pre[i] + (rows + kGainRows - 1) / kGainRows;
         T.h.cls_pre[i + 1] = T.h.cls_pre[i] + (int)((px + ctile - 1) / ctile);
         T.h.mor_pre[i + 1] = T.h.mor_pre[i] + (J.H + t.morph_rows - 1) / t.morph_rows;
     }

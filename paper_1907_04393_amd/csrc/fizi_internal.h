@@ -22,6 +22,8 @@ namespace fizi {
 constexpr int kMaxJobs = 256;          // jobs per table
 constexpr uint16_t kYrefClipped = 0xFFFFu;
 constexpr int kMaxMorphIters = 3;      // open_iters, close_iters <= 3
+constexpr int kGainSlots = 16;         // gain sums are spread over 16 accumulators
+constexpr int kGainRows = 4;           // sampled rows per gain tile
 
 // Skin-hue test on one RGB triple, without division (Section 3.1 (iii)).
 // For a hue a, let d_a be an RGB colour of hue a. The determinant
@@ -62,14 +64,16 @@ struct Job {
     int32_t delta, S1, open_it, close_it, min_area, fill_pm, glo, ghi;
     HueTest hue;
     // accumulators (zero when the table is uploaded)
-    unsigned long long num, den;   // gain sums over usable sampled pixels
+    // gain sums over usable sampled pixels, sampled row r adding to slot
+    // r % kGainSlots (fewer same-address atomics)
+    unsigned long long num[kGainSlots], den[kGainSlots];
     uint32_t nruns, flags;
 };
 
 struct TableHeader {
     int32_t njobs;
     int32_t pad0;
-    int32_t gain_pre[kMaxJobs + 1];   // sampled-row tiles
+    int32_t gain_pre[kMaxJobs + 1];   // gain tiles (kGainRows sampled rows)
     int32_t cls_pre[kMaxJobs + 1];    // classify tiles
     int32_t mor_pre[kMaxJobs + 1];    // morphology bands
     int32_t pad1;

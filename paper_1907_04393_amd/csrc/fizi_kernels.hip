@@ -95,6 +95,21 @@ __device__ __forceinline__ uint32_t inv_gain(unsigned long long num, unsigned lo
     return (uint32_t)q;
 }
 
+// The frame's inverse gain from its gain accumulators. `same_launch`: the
+// sums were written earlier in the same launch (persistent step), so they
+// are read with device-scope atomic loads; after a kernel boundary plain
+// (scalar) loads see them.
+__device__ __forceinline__ uint32_t job_gain(const Job *J, bool same_launch)
+{
+    unsigned long long n = 0, d = 0;
+#pragma unroll
+    for (int i = 0; i < kGainSlots; ++i) {
+        n += same_launch ? ld_dev(&J->num[i]) : J->num[i];
+        d += same_launch ? ld_dev(&J->den[i]) : J->den[i];
+    }
+    return inv_gain(n, d, J->glo, J->ghi);
+}
+
 // Skin-hue membership without division; see HueTest. Chroma > 0 is checked
 // by the caller.
 // Every factor fits the full-rate 24-bit signed multiply: |k| <= 6000,
@@ -169,36 +184,37 @@ __global__ __launch_bounds__(256) void k_make_yref(const uint8_t *__restrict__ f
 // ---------------------------------------------------------------------------
 // One sampled row of one frame: sums of reference and frame luminance over
 // its usable pixels, added to the frame's accumulators.
-__device__ __forceinline__ void gain_tile(Table *__restrict__ T, int nj, int t)
+__device__ __forceinline__ void gain_tile(Table *__restrict__ T, int j, int tile)
 {
     __shared__ uint32_t s_num[256 / kWave], s_den[256 / kWave];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int j = find_job(T->h.gain_pre, nj, t);
     Job *J = &T->jobs[j];
-    const int rr = t - T->h.gain_pre[j];
     const int W = J->W;
-    const GLOBAL uint32_t *row = G(reinterpret_cast<const uint32_t *>(J->frame + (size_t)rr * J->rs * W * 3));
-    const GLOBAL uint64_t *yr = G(reinterpret_cast<const uint64_t *>(J->yref + (size_t)rr * W));
+    const int rows = (J->H + J->rs - 1) / J->rs;
     const HueTest h = J->hue;
     uint32_t num = 0, den = 0;
-    for (int g = threadIdx.x; g < W / 4; g += blockDim.x) {
-        const uint32_t w0 = row[3 * g], w1 = row[3 * g + 1], w2 = row[3 * g + 2];
-        const uint64_t yv = yr[g];
+    for (int rr = tile * kGainRows; rr < min(rows, (tile + 1) * kGainRows); ++rr) {
+        const GLOBAL uint32_t *row = G(reinterpret_cast<const uint32_t *>(J->frame + (size_t)rr * J->rs * W * 3));
+        const GLOBAL uint64_t *yr = G(reinterpret_cast<const uint64_t *>(J->yref + (size_t)rr * W));
+        for (int g = threadIdx.x; g < W / 4; g += blockDim.x) {
+            const uint32_t w0 = row[3 * g], w1 = row[3 * g + 1], w2 = row[3 * g + 2];
+            const uint64_t yv = yr[g];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t r = byte_of(w0, w1, w2, 3 * k), gg = byte_of(w0, w1, w2, 3 * k + 1),
-                           b = byte_of(w0, w1, w2, 3 * k + 2);
-            const uint32_t y = (uint32_t)(yv >> (16 * k)) & 0xFFFFu;
-            bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
-            if (ok) {
-                const int mx = max(max((int)r, (int)gg), (int)b);
-                const int mn = min(min((int)r, (int)gg), (int)b);
-                if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
-                    ok = false;
-            }
-            if (ok) {
-                num += y;
-                den += r + 2 * gg + b;
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t r = byte_of(w0, w1, w2, 3 * k), gg = byte_of(w0, w1, w2, 3 * k + 1),
+                               b = byte_of(w0, w1, w2, 3 * k + 2);
+                const uint32_t y = (uint32_t)(yv >> (16 * k)) & 0xFFFFu;
+                bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
+                if (ok) {
+                    const int mx = max(max((int)r, (int)gg), (int)b);
+                    const int mn = min(min((int)r, (int)gg), (int)b);
+                    if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
+                        ok = false;
+                }
+                if (ok) {
+                    num += y;
+                    den += r + 2 * gg + b;
+                }
             }
         }
     }
@@ -215,18 +231,35 @@ __device__ __forceinline__ void gain_tile(Table *__restrict__ T, int nj, int t)
             n += s_num[w];
             d += s_den[w];
         }
-        atomicAdd(&J->num, n);
-        atomicAdd(&J->den, d);
+        const int slot = tile & (kGainSlots - 1);
+        atomicAdd(&J->num[slot], n);
+        atomicAdd(&J->den[slot], d);
     }
     __syncthreads();
 }
 
+// Tiles [t0, t1) of this block, in order, each with its job. Contiguous
+// ranges keep a block's consecutive tiles in one frame, so the job is found
+// by one search and then advanced.
+template <typename F>
+__device__ __forceinline__ void for_block_tiles(const int32_t *pre, int nj, F f)
+{
+    const int total = pre[nj];
+    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int t0 = (int)blockIdx.x * per, t1 = min(total, t0 + per);
+    if (t0 >= t1)
+        return;
+    int j = find_job(pre, nj, t0);
+    for (int t = t0; t < t1; ++t) {
+        while (t >= pre[j + 1])
+            ++j;
+        f(j, t - pre[j]);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_gain(Table *__restrict__ T)
 {
-    const int nj = T->h.njobs;
-    const int total = T->h.gain_pre[nj];
-    for (int t = blockIdx.x; t < total; t += gridDim.x)
-        gain_tile(T, nj, t);
+    for_block_tiles(T->h.gain_pre, T->h.njobs, [&](int j, int tile) { gain_tile(T, j, tile); });
 }
 
 // ---------------------------------------------------------------------------
@@ -236,7 +269,7 @@ __global__ __launch_bounds__(256) void k_minmax(Table *__restrict__ T, int nj,
 {
     __shared__ uint32_t s_inv[kMaxJobs];
     for (int j = threadIdx.x; j < nj; j += blockDim.x)
-        s_inv[j] = inv_gain(T->jobs[j].num, T->jobs[j].den, T->jobs[j].glo, T->jobs[j].ghi);
+        s_inv[j] = job_gain(&T->jobs[j], false);
     __syncthreads();
     const int ngroups = npx / 4;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += gridDim.x * blockDim.x) {
@@ -290,14 +323,12 @@ __global__ __launch_bounds__(256) void k_minmax(Table *__restrict__ T, int nj,
 // tests only run for pixels already outside the background box, so waves of
 // pure background skip them.
 template <int ITERS>
-__device__ __forceinline__ void classify_tile(Table *__restrict__ T, int nj, int t)
+__device__ __forceinline__ void classify_tile(Table *__restrict__ T, int j, int tile, bool same_launch)
 {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int j = find_job(T->h.cls_pre, nj, t);
     const Job *J = &T->jobs[j];
-    const int tile = t - T->h.cls_pre[j];
     const uint32_t npx = (uint32_t)J->W * (uint32_t)J->H;
-    const uint32_t inv = inv_gain(ld_dev(&J->num), ld_dev(&J->den), J->glo, J->ghi);
+    const uint32_t inv = job_gain(J, same_launch);
     const int delta = J->delta, S1 = J->S1;
     const HueTest h = J->hue;
     const GLOBAL uint32_t *fr = G(reinterpret_cast<const uint32_t *>(J->frame));
@@ -353,10 +384,7 @@ __device__ __forceinline__ void classify_tile(Table *__restrict__ T, int nj, int
 template <int ITERS>
 __global__ __launch_bounds__(256) void k_classify(Table *__restrict__ T)
 {
-    const int nj = T->h.njobs;
-    const int total = T->h.cls_pre[nj];
-    for (int t = blockIdx.x; t < total; t += gridDim.x)
-        classify_tile<ITERS>(T, nj, t);
+    for_block_tiles(T->h.cls_pre, T->h.njobs, [&](int j, int tile) { classify_tile<ITERS>(T, j, tile, false); });
 }
 
 // ---------------------------------------------------------------------------
@@ -508,153 +536,376 @@ __device__ __forceinline__ void link_up(GLOBAL uint32_t *parent, P above, int Wd
     }
 }
 
-// One workgroup per band of R mask rows: opening and closing in LDS, the
-// band's I_FIZI rows, its runs, and the union-find of the runs inside the
-// band (every run then points straight at its band-local root).
-template <int R>
-__device__ __forceinline__ void morph_tile(Table *__restrict__ T, int nj, int t, uint64_t *lds,
-                                           int buf_words)
+// ---------------------------------------------------------------------------
+// Morphology, runs and band-local components: one wave per band of R mask
+// rows. Lane l holds words l and l + 64 of a row (W <= 8192). The band's rows,
+// with 2(o+c) halo rows on each side, stream once through a pipeline of the
+// opening/closing stages held in registers: each stage keeps the two rows
+// before its input, and on input row i emits row i - 1 from the 3x3 window
+// (vertical AND/OR per word, horizontal neighbours from the words' edge bits,
+// exchanged between lanes). Rows outside the image enter a stage as its
+// neutral value (1 for erosion, 0 for dilation), which is exactly the border
+// rule; halo rows inside the image only corrupt rows outside the band. Each
+// final row of the band is stored (I_FIZI), its runs are appended to the
+// frame's run list, and the runs are joined to the touching runs of the row
+// above in a union-find over band-local run indices kept in LDS (indices grow
+// in raster order, so a root is its component's first run in the band).
+// Rows are processed in order, so trees stay shallow. A band with more runs
+// than the LDS table holds falls back to the same union-find in global
+// memory, reading the rows back from I_FIZI.
+constexpr int kMaxRowWords = 128;          // W <= 8192
+constexpr int kBandRunsLds = 512;
+constexpr int kRawChunk = 4;               // rows loaded together (the selects below assume 4)
+
+struct WaveLds {
+    uint64_t rows[2][kMaxRowWords];        // the last two final rows
+    uint32_t pref[2][kMaxRowWords];        // run starts before each word
+    uint32_t start[kBandRunsLds];          // start pixel of band run k
+    uint32_t par[kBandRunsLds];            // union-find parent (band index)
+};
+
+__device__ __forceinline__ void wave_sync()
 {
-    __shared__ uint32_t s_wave[256 / kWave];
-    __shared__ uint32_t s_base;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, kWave);
+        if (lane >= o)
+            v += t;
+    }
+    return v;
+}
+
+// Edge bits of the neighbouring words of this lane's NC words (word
+// lane + 64 q): bit 63 of the word on the left (lc) and bit 0 of the word on
+// the right (rc); words outside [0, Wd) give `edge`.
+template <int NC>
+__device__ __forceinline__ void row_carries(const uint64_t *v, int Wd, uint32_t edge, uint32_t *lc, uint32_t *rc)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t hi0 = (uint32_t)(v[0] >> 63), lo0 = (uint32_t)v[0] & 1u;
+    const uint32_t up0 = __shfl_up(hi0, 1, kWave), dn0 = __shfl_down(lo0, 1, kWave);
+    lc[0] = lane == 0 ? edge : up0;
+    if (NC == 1) {
+        rc[0] = (lane + 1 < Wd) ? dn0 : edge;
+    } else {
+        const uint32_t hi1 = (uint32_t)(v[NC - 1] >> 63), lo1 = (uint32_t)v[NC - 1] & 1u;
+        const uint32_t up1 = __shfl_up(hi1, 1, kWave), dn1 = __shfl_down(lo1, 1, kWave);
+        const uint32_t last_hi0 = __shfl(hi0, kWave - 1, kWave), first_lo1 = __shfl(lo1, 0, kWave);
+        rc[0] = (lane + 1 < Wd) ? (lane == kWave - 1 ? first_lo1 : dn0) : edge;
+        lc[NC - 1] = lane == 0 ? last_hi0 : up1;
+        rc[NC - 1] = (lane + kWave + 1 < Wd) ? dn1 : edge;
+    }
+}
+
+// One erosion (ero) or dilation of row b given the rows above (a) and below (c).
+template <int NC>
+__device__ __forceinline__ void morph_row(bool ero, const uint64_t *a, const uint64_t *b, const uint64_t *c, int Wd,
+                                          uint64_t *out)
+{
+    uint64_t v[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+        v[q] = ero ? (a[q] & b[q] & c[q]) : (a[q] | b[q] | c[q]);
+    uint32_t lc[NC], rc[NC];
+    row_carries<NC>(v, Wd, ero ? 1u : 0u, lc, rc);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        const uint64_t left = (v[q] << 1) | lc[q];
+        const uint64_t right = (v[q] >> 1) | ((uint64_t)rc[q] << 63);
+        out[q] = ero ? (v[q] & left & right) : (v[q] | left | right);
+    }
+}
+
+__device__ __forceinline__ uint32_t find_lds(uint32_t *par, uint32_t x)
+{
+    uint32_t p = __hip_atomic_load(par + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    while (p != x) {
+        x = p;
+        p = __hip_atomic_load(par + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    return x;
+}
+
+__device__ __forceinline__ void unite_lds(uint32_t *par, uint32_t a, uint32_t b)
+{
+    for (;;) {
+        a = find_lds(par, a);
+        b = find_lds(par, b);
+        if (a == b)
+            return;
+        if (a > b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        const uint32_t old = __hip_atomic_fetch_min(par + b, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (old == b)
+            return;
+        b = old;
+    }
+}
+
+// Band-local index of the run of `row` (LDS) that starts at bit bs.
+__device__ __forceinline__ uint32_t run_index(const uint64_t *row, const uint32_t *pref, uint32_t first, int bs)
+{
+    const int w = bs >> 6, b = bs & 63;
+    const uint64_t word = row[w];
+    const uint64_t prev = w > 0 ? row[w - 1] : 0ull;
+    const uint64_t st = word & ~((word << 1) | (prev >> 63));
+    return first + pref[w] + (uint32_t)__popcll(st & ((1ull << b) - 1ull));
+}
+
+__device__ __forceinline__ bool stage_erodes(int k, int oi, int ci) { return (k < oi) || (k >= 2 * oi + ci); }
+
+// KMAX: most opening/closing stages a job may have; NC: words per lane.
+template <int KMAX, int NC>
+__device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t, WaveLds &L)
+{
+    const int lane = threadIdx.x & (kWave - 1);
     const int j = find_job(T->h.mor_pre, nj, t);
     Job *J = &T->jobs[j];
     const int band = t - T->h.mor_pre[j];
-    const int W = J->W, H = J->H, Wd = J->Wd;
+    const int W = J->W, H = J->H, Wd = J->Wd, R = J->band;
     const int oi = J->open_it, ci = J->close_it;
-    const int nops = 2 * (oi + ci);
+    const int K = 2 * (oi + ci);
     const int y0 = band * R, y1 = min(y0 + R, H);
-    const int ya = max(0, y0 - nops), yb = min(H, y1 + nops);
-    uint64_t *A = lds, *B = lds + buf_words;
-    const GLOBAL uint64_t *src = G(J->raw) + (size_t)ya * Wd;
-    for (int i = threadIdx.x; i < (yb - ya) * Wd; i += blockDim.x)
-        A[i] = src[i];
-    __syncthreads();
-    int va = ya, vb = yb;
-    for (int op = 0; op < nops; ++op) {
-        const bool ero = (op < oi) || (op >= 2 * oi + ci);
-        const uint64_t neutral = ero ? ~0ull : 0ull;
-        const int na = (va == 0) ? 0 : va + 1;
-        const int nb = (vb == H) ? H : vb - 1;
-        for (int i = threadIdx.x; i < (nb - na) * Wd; i += blockDim.x) {
-            const int r = na + i / Wd, w = i - (i / Wd) * Wd;
-            uint64_t v[3];
-#pragma unroll
-            for (int d = -1; d <= 1; ++d) {
-                const int ww = w + d;
-                uint64_t acc;
-                if (ww < 0 || ww >= Wd) {
-                    acc = neutral;
-                } else {
-                    const uint64_t up = (r - 1 >= 0) ? A[(r - 1 - ya) * Wd + ww] : neutral;
-                    const uint64_t mid = A[(r - ya) * Wd + ww];
-                    const uint64_t dn = (r + 1 < H) ? A[(r + 1 - ya) * Wd + ww] : neutral;
-                    acc = ero ? (up & mid & dn) : (up | mid | dn);
-                }
-                v[d + 1] = acc;
-            }
-            const uint64_t left = (v[1] << 1) | (v[0] >> 63);
-            const uint64_t right = (v[1] >> 1) | (v[2] << 63);
-            B[(r - ya) * Wd + w] = ero ? (v[1] & left & right) : (v[1] | left | right);
-        }
-        __syncthreads();
-        uint64_t *tmp = A;
-        A = B;
-        B = tmp;
-        va = na;
-        vb = nb;
-    }
-    // I_FIZI rows of the band
-    const uint64_t *fin = A + (size_t)(y0 - ya) * Wd;
-    GLOBAL uint64_t *dst = G(J->fizi) + (size_t)y0 * Wd;
-    const int nwords = (y1 - y0) * Wd;
-    for (int i = threadIdx.x; i < nwords; i += blockDim.x)
-        dst[i] = fin[i];
-    // runs of the band: count, reserve, emit
-    uint32_t cnt = 0;
-    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
-        const int w = i % Wd;
-        const uint64_t word = fin[i];
-        const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
-        cnt += (uint32_t)__popcll(word & ~((word << 1) | (prev >> 63)));
-    }
-    uint32_t band_total;
-    uint32_t off = block_excl_scan(cnt, s_wave, &band_total);
-    if (threadIdx.x == 0)
-        s_base = band_total ? atomicAdd(&J->nruns, band_total) : 0u;
-    __syncthreads();
-    uint32_t idx = s_base + off;
-    const uint32_t cap = J->run_cap;
-    if (threadIdx.x == 0 && s_base + band_total > cap)
-        atomicOr(&J->flags, 1u);
+    const int ya = max(0, y0 - K), yb = min(H, y1 + K);
+    const GLOBAL uint64_t *raw = G(J->raw);
+    GLOBAL uint64_t *fz = G(J->fizi);
     GLOBAL uint32_t *parent = G(J->parent);
     GLOBAL uint32_t *area = G(J->area);
     GLOBAL uint64_t *runs = G(reinterpret_cast<uint64_t *>(J->runs));
-    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
-        const int rl = i / Wd, w = i - rl * Wd;
-        const uint64_t word = fin[i];
-        const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
-        uint64_t st = word & ~((word << 1) | (prev >> 63));
-        while (st) {
-            const int b = __builtin_ctzll(st);
-            st &= st - 1;
-            const int xs = 64 * w + b;
-            const int xe = run_end_lds(fin + (size_t)rl * Wd, Wd, w, b);
-            const uint32_t start = (uint32_t)(y0 + rl) * (uint32_t)W + (uint32_t)xs;
-            if (idx < cap) {
-                runs[idx] = ((uint64_t)(uint32_t)(xe - xs + 1) << 32) | start;
-                st_wg(parent + start, start);
-                area[start] = 0u;
+    const uint32_t cap = J->run_cap;
+    bool valid_w[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+        valid_w[q] = lane + kWave * q < Wd;
+
+    // pipeline state: the two rows before each stage's next input
+    uint64_t p2[KMAX][NC], p1[KMAX][NC];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+            p2[k][q] = p1[k][q] = stage_erodes(k, oi, ci) ? ~0ull : 0ull;
+    uint32_t nband = 0, prev_first = 0;
+    bool prev_nonempty = false, over = false;
+    const int nsteps = (y1 - ya) + K;
+    uint64_t xb[kRawChunk][NC];
+#pragma unroll 1
+    for (int s = 0; s < nsteps; ++s) {
+        const int q = s & (kRawChunk - 1);
+        if (q == 0) {
+            // the next kRawChunk input rows, loaded together
+#pragma unroll
+            for (int qq = 0; qq < kRawChunk; ++qq) {
+                const int r = ya + s + qq;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    xb[qq][c] = (r < yb && valid_w[c]) ? raw[(size_t)r * Wd + lane + kWave * c] : 0ull;
             }
-            ++idx;
+        }
+        {
+            uint64_t x[NC];
+            const bool past = ya + s >= yb;
+            const uint64_t n0 = (K > 0 && stage_erodes(0, oi, ci)) ? ~0ull : 0ull;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const uint64_t v = q == 0 ? xb[0][c] : (q == 1 ? xb[1][c] : (q == 2 ? xb[2][c] : xb[3][c]));
+                x[c] = past ? n0 : v;
+            }
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (k < K) {
+                    const bool ero = stage_erodes(k, oi, ci);
+                    const int i = ya + s - k;
+                    if (i < 0 || i >= H) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            x[c] = ero ? ~0ull : 0ull;
+                    }
+                    uint64_t o[NC];
+                    morph_row<NC>(ero, p2[k], p1[k], x, Wd, o);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        p2[k][c] = p1[k][c];
+                        p1[k][c] = x[c];
+                    }
+                    const int jr = i - 1;
+                    const bool oob = k + 1 < K && (jr < 0 || jr >= H);
+                    const uint64_t n1 = stage_erodes(k + 1, oi, ci) ? ~0ull : 0ull;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        x[c] = oob ? n1 : o[c];
+                }
+            }
+            const int jrow = ya + s - K;
+            if (jrow < y0 || jrow >= y1)
+                continue;
+            // a final I_FIZI row
+            GLOBAL uint64_t *frow = fz + (size_t)jrow * Wd;
+            uint64_t orw = 0ull;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (valid_w[c])
+                    frow[lane + kWave * c] = x[c];
+                else
+                    x[c] = 0ull;
+                orw |= x[c];
+            }
+            if (__ballot(orw != 0ull) == 0ull) {
+                prev_nonempty = false;
+                continue;
+            }
+            const int cur = (jrow - y0) & 1;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (valid_w[c])
+                    L.rows[cur][lane + kWave * c] = x[c];
+            uint32_t lcs[NC], rcs[NC];
+            row_carries<NC>(x, Wd, 0u, lcs, rcs);
+            uint64_t st[NC];
+            uint32_t ex[NC];
+            uint32_t total = 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                st[c] = x[c] & ~((x[c] << 1) | lcs[c]);
+                const uint32_t n = (uint32_t)__popcll(st[c]);
+                const uint32_t inc = wave_incl_scan(n);
+                ex[c] = total + inc - n;
+                total += __shfl(inc, kWave - 1, kWave);
+                if (valid_w[c])
+                    L.pref[cur][lane + kWave * c] = ex[c];
+            }
+            uint32_t gbase = 0;
+            if (lane == 0)
+                gbase = atomicAdd(&J->nruns, total);
+            gbase = __shfl(gbase, 0, kWave);
+            if (lane == 0 && gbase + total > cap)
+                atomicOr(&J->flags, 1u);
+            wave_sync();
+            const bool use_lds = !over && nband + total <= (uint32_t)kBandRunsLds;
+            // emit the row's runs
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                uint64_t m = st[c];
+                const int w = lane + kWave * c;
+                while (m) {
+                    const int b = __builtin_ctzll(m);
+                    const uint32_t k = ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
+                    m &= m - 1;
+                    const int xs = 64 * w + b;
+                    const int xe = run_end_lds(L.rows[cur], Wd, w, b);
+                    const uint32_t start = (uint32_t)jrow * (uint32_t)W + (uint32_t)xs;
+                    if (gbase + k < cap) {
+                        runs[gbase + k] = ((uint64_t)(uint32_t)(xe - xs + 1) << 32) | start;
+                        st_wg(parent + start, start);
+                        area[start] = 0u;
+                    }
+                    if (use_lds) {
+                        L.start[nband + k] = start;
+                        L.par[nband + k] = nband + k;
+                    }
+                }
+            }
+            wave_sync();
+            // join with the touching runs of the row above (same band)
+            if (use_lds && prev_nonempty && jrow > y0) {
+                const int prv = cur ^ 1;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    uint64_t m = st[c];
+                    const int w = lane + kWave * c;
+                    while (m) {
+                        const int b = __builtin_ctzll(m);
+                        const uint32_t k = nband + ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
+                        m &= m - 1;
+                        const int xs = 64 * w + b;
+                        const int xe = run_end_lds(L.rows[cur], Wd, w, b);
+                        const int hi = min(xe + 1, W - 1);
+                        int pos = max(xs - 1, 0);
+                        while (pos <= hi) {
+                            const int xb2 = next_one(L.rows[prv], pos, hi);
+                            if (xb2 < 0)
+                                break;
+                            const int bs = prev_zero(L.rows[prv], xb2) + 1;
+                            unite_lds(L.par, k, run_index(L.rows[prv], L.pref[prv], prev_first, bs));
+                            pos = next_zero(L.rows[prv], Wd, xb2) + 1;
+                        }
+                    }
+                }
+                wave_sync();
+            }
+            if (!use_lds)
+                over = true;
+            prev_first = nband;
+            nband += total;
+            prev_nonempty = true;
         }
     }
-    __syncthreads();
-    // union-find inside the band: each run below the band's first row
-    // joins the runs it touches in the row above
-    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
-        const int rl = i / Wd, w = i - rl * Wd;
-        if (rl == 0)
-            continue;
-        const uint64_t word = fin[i];
-        const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
-        uint64_t st = word & ~((word << 1) | (prev >> 63));
-        while (st) {
-            const int b = __builtin_ctzll(st);
-            st &= st - 1;
-            const int xs = 64 * w + b;
-            const int xe = run_end_lds(fin + (size_t)rl * Wd, Wd, w, b);
-            const uint32_t start = (uint32_t)(y0 + rl) * (uint32_t)W + (uint32_t)xs;
-            link_up(parent, fin + (size_t)(rl - 1) * Wd, Wd, W, y0 + rl, xs, xe, start);
+    if (!over) {
+        // every run of the band points at the band root's start pixel
+        for (uint32_t k = lane; k < nband; k += kWave) {
+            const uint32_t r = find_lds(L.par, k);
+            if (r != k)
+                st_wg(parent + L.start[k], L.start[r]);
+        }
+        return;
+    }
+    // too many runs for LDS: the same union-find over the band in global memory
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (int jr = y0 + 1; jr < y1; ++jr) {
+        const GLOBAL uint64_t *row = fz + (size_t)jr * Wd;
+        for (int w = lane; w < Wd; w += kWave) {
+            const uint64_t word = row[w];
+            const uint64_t prev = w > 0 ? row[w - 1] : 0ull;
+            uint64_t m = word & ~((word << 1) | (prev >> 63));
+            while (m) {
+                const int b = __builtin_ctzll(m);
+                m &= m - 1;
+                const int xs = 64 * w + b;
+                int xe = xs;
+                while (xe + 1 < W && ((row[(xe + 1) >> 6] >> ((xe + 1) & 63)) & 1ull))
+                    ++xe;
+                link_up(parent, row - Wd, Wd, W, jr, xs, xe, (uint32_t)jr * (uint32_t)W + (uint32_t)xs);
+            }
         }
     }
-    __syncthreads();
-    // every run of the band points at its band root
-    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
-        const int rl = i / Wd, w = i - rl * Wd;
-        const uint64_t word = fin[i];
-        const uint64_t prev = w > 0 ? fin[i - 1] : 0ull;
-        uint64_t st = word & ~((word << 1) | (prev >> 63));
-        while (st) {
-            const int b = __builtin_ctzll(st);
-            st &= st - 1;
-            const uint32_t start = (uint32_t)(y0 + rl) * (uint32_t)W + (uint32_t)(64 * w + b);
-            const uint32_t root = find_root(parent, start);
-            if (root != start)
-                st_wg(parent + start, root);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (int jr = y0; jr < y1; ++jr) {
+        const GLOBAL uint64_t *row = fz + (size_t)jr * Wd;
+        for (int w = lane; w < Wd; w += kWave) {
+            const uint64_t word = row[w];
+            const uint64_t prev = w > 0 ? row[w - 1] : 0ull;
+            uint64_t m = word & ~((word << 1) | (prev >> 63));
+            while (m) {
+                const int b = __builtin_ctzll(m);
+                m &= m - 1;
+                const uint32_t start = (uint32_t)jr * (uint32_t)W + (uint32_t)(64 * w + b);
+                const uint32_t root = find_root(parent, start);
+                if (root != start)
+                    st_wg(parent + start, root);
+            }
         }
     }
-    __syncthreads();
 }
 
-template <int R>
-__global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T, int buf_words)
+template <int KMAX, int NC>
+__global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T)
 {
-    extern __shared__ uint64_t lds[];
+    __shared__ WaveLds s_wl[256 / kWave];
+    const int wave = threadIdx.x / kWave;
     const int nj = T->h.njobs;
     const int total = T->h.mor_pre[nj];
-    for (int t = blockIdx.x; t < total; t += gridDim.x)
-        morph_tile<R>(T, nj, t, lds, buf_words);
+    for (int t = blockIdx.x * (256 / kWave) + wave; t < total; t += gridDim.x * (256 / kWave))
+        morph_band<KMAX, NC>(T, nj, t, s_wl[wave]);
 }
 
 // ---------------------------------------------------------------------------
@@ -685,7 +936,7 @@ struct OpMin { template <typename T> __device__ T operator()(T a, T b) const { r
 // One workgroup per frame: joins the band-local trees across band borders,
 // then finds roots, areas, the hand zone (largest area, ties to the smallest
 // first index), its sums and box, and writes the pointer.
-__device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j)
+__device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool same_launch)
 {
     __shared__ unsigned long long s_u64[kMaxWaves];
     __shared__ uint32_t s_u32[kMaxWaves];
@@ -697,7 +948,7 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j)
     GLOBAL uint32_t *area = G(J->area);
     const GLOBAL uint64_t *fz = G(J->fizi);
     GLOBAL uint64_t *hand = J->hand ? G(J->hand) : nullptr;
-    const uint32_t inv = inv_gain(ld_dev(&J->num), ld_dev(&J->den), J->glo, J->ghi);
+    const uint32_t inv = job_gain(J, same_launch);
     if (hand)
         for (int i = threadIdx.x; i < H * Wd; i += blockDim.x)
             hand[i] = 0ull;
@@ -802,7 +1053,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(Table *__restrict__
 {
     const int nj = T->h.njobs;
     for (int j = blockIdx.x; j < nj; j += gridDim.x)
-        resolve_job(T, j);
+        resolve_job(T, j, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -841,25 +1092,25 @@ __device__ __forceinline__ bool grid_sync(PersistState *ps, unsigned k)
     return s_ok != 0;
 }
 
-template <int ITERS, int R>
-__global__ __launch_bounds__(256) void k_step(Table *__restrict__ T, int buf_words, PersistState *ps)
+template <int ITERS, int KMAX, int NC>
+__global__ __launch_bounds__(256) void k_step(Table *__restrict__ T, PersistState *ps)
 {
-    extern __shared__ uint64_t lds[];
     const int nj = T->h.njobs;
-    for (int t = blockIdx.x; t < T->h.gain_pre[nj]; t += gridDim.x)
-        gain_tile(T, nj, t);
+    for_block_tiles(T->h.gain_pre, nj, [&](int j, int tile) { gain_tile(T, j, tile); });
     bool ok = grid_sync(ps, 1);
     if (ok)
-        for (int t = blockIdx.x; t < T->h.cls_pre[nj]; t += gridDim.x)
-            classify_tile<ITERS>(T, nj, t);
+        for_block_tiles(T->h.cls_pre, nj, [&](int j, int tile) { classify_tile<ITERS>(T, j, tile, true); });
     ok = grid_sync(ps, 2) && ok;
-    if (ok)
-        for (int t = blockIdx.x; t < T->h.mor_pre[nj]; t += gridDim.x)
-            morph_tile<R>(T, nj, t, lds, buf_words);
+    if (ok) {
+        __shared__ WaveLds s_wl[256 / kWave];
+        const int wave = threadIdx.x / kWave;
+        for (int t = blockIdx.x * (256 / kWave) + wave; t < T->h.mor_pre[nj]; t += gridDim.x * (256 / kWave))
+            morph_band<KMAX, NC>(T, nj, t, s_wl[wave]);
+    }
     ok = grid_sync(ps, 3) && ok;
     if (ok)
         for (int j = blockIdx.x; j < nj; j += gridDim.x)
-            resolve_job(T, j);
+            resolve_job(T, j, true);
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned done = atomicAdd(&ps->finished, 1u);
@@ -940,17 +1191,18 @@ hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max
 {
     if (total_tiles <= 0)
         return hipSuccess;
-    const int rows = t.morph_rows + 2 * max_ops;
-    const int buf_words = rows * max_wd;
-    const uint32_t lds = (uint32_t)(2 * (size_t)buf_words * sizeof(uint64_t));
-    const int grid = min(total_tiles, n_cu * 4);
+    const int waves = 256 / kWave;
+    const int grid = min((total_tiles + waves - 1) / waves, n_cu * t.grid_per_cu);
     Table *tab = const_cast<Table *>(d_tab);
-    switch (t.morph_rows) {
-    case 8: FIZI_LAUNCH(k_morph<8>, grid, 256, lds, s, ev, tab, buf_words); break;
-    case 16: FIZI_LAUNCH(k_morph<16>, grid, 256, lds, s, ev, tab, buf_words); break;
-    case 64: FIZI_LAUNCH(k_morph<64>, grid, 256, lds, s, ev, tab, buf_words); break;
-    default: FIZI_LAUNCH(k_morph<32>, grid, 256, lds, s, ev, tab, buf_words); break;
-    }
+    const bool wide = max_wd > kWave, deep = max_ops > 4;
+    if (!wide && !deep)
+        FIZI_LAUNCH((k_morph<4, 1>), grid, 256, 0, s, ev, tab);
+    else if (!wide)
+        FIZI_LAUNCH((k_morph<4 * kMaxMorphIters, 1>), grid, 256, 0, s, ev, tab);
+    else if (!deep)
+        FIZI_LAUNCH((k_morph<4, 2>), grid, 256, 0, s, ev, tab);
+    else
+        FIZI_LAUNCH((k_morph<4 * kMaxMorphIters, 2>), grid, 256, 0, s, ev, tab);
     return hipGetLastError();
 }
 
@@ -966,56 +1218,55 @@ hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEve
 // allow (wave64, 512 VGPRs per SIMD lane in granules of 8, four SIMDs and
 // 160 KiB of LDS per CU, eight waves per SIMD), capped at four so that the
 // whole grid is resident with room to spare.
-template <int ITERS, int R>
-int step_blocks_per_cu(uint32_t lds)
+template <int ITERS, int KMAX, int NC>
+int step_blocks_per_cu()
 {
     hipFuncAttributes a{};
-    if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(k_step<ITERS, R>)) != hipSuccess)
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(k_step<ITERS, KMAX, NC>)) != hipSuccess)
         return 1;
     const int vgpr = std::max(8, (a.numRegs + 7) / 8 * 8);
     const int waves_per_simd = std::min(8, 512 / vgpr);     // one wave of each block per SIMD
-    const int by_lds = (int)((160 * 1024) / std::max<size_t>(1, lds + a.sharedSizeBytes));
+    const int by_lds = (int)((160 * 1024) / std::max<size_t>(1, a.sharedSizeBytes));
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<ITERS, R>, 256, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<ITERS, KMAX, NC>, 256, 0) != hipSuccess)
         nb = 1;
     return std::max(1, std::min(std::min(nb, 4), std::min(waves_per_simd, by_lds)));
 }
 
-template <int ITERS, int R>
-hipError_t launch_step_t(Table *tab, int buf_words, uint32_t lds, int n_cu, PersistState *ps, hipStream_t s,
-                         StageEvents ev)
+template <int ITERS, int KMAX, int NC>
+hipError_t launch_step_t(Table *tab, int n_cu, PersistState *ps, hipStream_t s, StageEvents ev)
 {
     static int per_cu = -1;
-    static uint32_t per_cu_lds = 0;
-    if (per_cu < 0 || per_cu_lds != lds) {
-        per_cu = step_blocks_per_cu<ITERS, R>(lds);
-        per_cu_lds = lds;
-    }
-    FIZI_LAUNCH((k_step<ITERS, R>), per_cu * n_cu, 256, lds, s, ev, tab, buf_words, ps);
+    if (per_cu < 0)
+        per_cu = step_blocks_per_cu<ITERS, KMAX, NC>();
+    FIZI_LAUNCH((k_step<ITERS, KMAX, NC>), per_cu * n_cu, 256, 0, s, ev, tab, ps);
     return hipGetLastError();
+}
+
+template <int ITERS>
+hipError_t launch_step_i(Table *tab, int max_wd, int max_ops, int n_cu, PersistState *ps, hipStream_t s,
+                         StageEvents ev)
+{
+    const bool wide = max_wd > kWave, deep = max_ops > 4;
+    if (!wide && !deep)
+        return launch_step_t<ITERS, 4, 1>(tab, n_cu, ps, s, ev);
+    if (!wide)
+        return launch_step_t<ITERS, 4 * kMaxMorphIters, 1>(tab, n_cu, ps, s, ev);
+    if (!deep)
+        return launch_step_t<ITERS, 4, 2>(tab, n_cu, ps, s, ev);
+    return launch_step_t<ITERS, 4 * kMaxMorphIters, 2>(tab, n_cu, ps, s, ev);
 }
 
 hipError_t launch_persistent(const Table *d_tab, int max_wd, int max_ops, int n_cu, const Tuning &t,
                              uint8_t *persist, hipStream_t s, StageEvents ev)
 {
-    const int rows = t.morph_rows + 2 * max_ops;
-    const int buf_words = rows * max_wd;
-    const uint32_t lds = (uint32_t)(2 * (size_t)buf_words * sizeof(uint64_t));
     Table *tab = const_cast<Table *>(d_tab);
     PersistState *ps = reinterpret_cast<PersistState *>(persist);
-#define FIZI_STEP_R(IT)                                                               \
-    switch (t.morph_rows) {                                                           \
-    case 8: return launch_step_t<IT, 8>(tab, buf_words, lds, n_cu, ps, s, ev);        \
-    case 16: return launch_step_t<IT, 16>(tab, buf_words, lds, n_cu, ps, s, ev);      \
-    case 64: return launch_step_t<IT, 64>(tab, buf_words, lds, n_cu, ps, s, ev);      \
-    default: return launch_step_t<IT, 32>(tab, buf_words, lds, n_cu, ps, s, ev);      \
-    }
     switch (t.cls_iters) {
-    case 2: FIZI_STEP_R(2)
-    case 8: FIZI_STEP_R(8)
-    default: FIZI_STEP_R(4)
+    case 2: return launch_step_i<2>(tab, max_wd, max_ops, n_cu, ps, s, ev);
+    case 8: return launch_step_i<8>(tab, max_wd, max_ops, n_cu, ps, s, ev);
+    default: return launch_step_i<4>(tab, max_wd, max_ops, n_cu, ps, s, ev);
     }
-#undef FIZI_STEP_R
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s)

@@ -33,7 +33,7 @@ __device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftP
     o.ur = fmaf(s.p_br, db, s.p_rr * dr);
     o.d = sqrtf(fmaxf(fmaf(db, o.ub, dr * o.ur), 0.0f));
     o.z = (s.theta - o.d) * s.inv_t;
-    o.m = 1.0f / (1.0f + expf(-o.z));
+    o.m = __frcp_rn(1.0f + __expf(-o.z));   // hardware exp2 / reciprocal, ~1 ulp
     return o;
 }
 
@@ -64,28 +64,28 @@ __global__ __launch_bounds__(256) void k_soft_fwd(const uint8_t *__restrict__ fr
     }
 }
 
-// Adds one pixel's contributions: dL/dz is gz; its loss term when y >= 0.
-__device__ __forceinline__ void soft_acc(const SoftPx &o, float gz, float inv_t, double *acc)
+// Adds one pixel's contributions (FP32) to acc: dL/dz is gz.
+__device__ __forceinline__ void soft_acc(const SoftPx &o, float gz, float inv_t, float *acc)
 {
     const float gd = -gz * inv_t;
-    const float gq = o.d > 0.0f ? gd / (2.0f * o.d) : 0.0f;
-    acc[0] += (double)(gq * (-2.0f * o.ub));
-    acc[1] += (double)(gq * (-2.0f * o.ur));
-    acc[2] += (double)(gq * (-o.ub * o.ub));
-    acc[3] += (double)(gq * (-2.0f * o.ub * o.ur));
-    acc[4] += (double)(gq * (-o.ur * o.ur));
-    acc[5] += (double)(gz * inv_t);
+    const float gq = o.d > 0.0f ? gd * __frcp_rn(2.0f * o.d) : 0.0f;
+    acc[0] += gq * (-2.0f * o.ub);
+    acc[1] += gq * (-2.0f * o.ur);
+    acc[2] += gq * (-o.ub * o.ub);
+    acc[3] += gq * (-2.0f * o.ub * o.ur);
+    acc[4] += gq * (-o.ur * o.ur);
+    acc[5] += gz * inv_t;
 }
 
 // dL/dz of one pixel: from the upstream dL/dm, or (fused BCE) (m - y) / N,
 // which also adds the pixel's BCE term to acc[6].
 __device__ __forceinline__ float soft_gz(const SoftPx &o, const float *dLdm, const uint8_t *gt, long long i,
-                                         float inv_n, double *acc)
+                                         float inv_n, float *acc)
 {
     if (dLdm)
         return dLdm[i] * o.m * (1.0f - o.m);
     const float y = gt[i] ? 1.0f : 0.0f;
-    acc[6] += (double)(fmaxf(o.z, 0.0f) - o.z * y + log1pf(expf(-fabsf(o.z))));
+    acc[6] += fmaxf(o.z, 0.0f) - o.z * y + __logf(1.0f + __expf(-fabsf(o.z)));
     return (o.m - y) * inv_n;
 }
 
@@ -100,17 +100,24 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ fr
     for (long long gi = blockIdx.x * (long long)blockDim.x + threadIdx.x; gi < groups;
          gi += (long long)gridDim.x * blockDim.x) {
         const uint32_t w0 = f[3 * gi], w1 = f[3 * gi + 1], w2 = f[3 * gi + 2];
+        float a4[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};   // the 4 pixels in FP32
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const SoftPx o = soft_px(byte_at(w0, w1, w2, 3 * k), byte_at(w0, w1, w2, 3 * k + 1),
                                      byte_at(w0, w1, w2, 3 * k + 2), s);
-            soft_acc(o, soft_gz(o, dLdm, gt, 4 * gi + k, inv_n, acc), s.inv_t, acc);
+            soft_acc(o, soft_gz(o, dLdm, gt, 4 * gi + k, inv_n, a4), s.inv_t, a4);
         }
+#pragma unroll
+        for (int k = 0; k < kSoftOut - 1; ++k)
+            acc[k] += (double)a4[k];
     }
     if (blockIdx.x == 0 && threadIdx.x < (unsigned)(npx - 4 * groups)) {
         const long long i = 4 * groups + threadIdx.x;
+        float a1[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};
         const SoftPx o = soft_px(frames[3 * i], frames[3 * i + 1], frames[3 * i + 2], s);
-        soft_acc(o, soft_gz(o, dLdm, gt, i, inv_n, acc), s.inv_t, acc);
+        soft_acc(o, soft_gz(o, dLdm, gt, i, inv_n, a1), s.inv_t, a1);
+        for (int k = 0; k < kSoftOut - 1; ++k)
+            acc[k] += (double)a1[k];
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x / 64;
 #pragma unroll
@@ -178,7 +185,7 @@ int soft_grid(long long npx)
     if (device_cu_count(&dev, &n_cu) != FIZI_OK)
         n_cu = 256;
     const long long groups = (npx / 4 + 255) / 256;
-    return (int)std::max<long long>(1, std::min<long long>(std::min(kSoftBlocksMax, n_cu * 4), groups));
+    return (int)std::max<long long>(1, std::min<long long>(std::min(kSoftBlocksMax, n_cu * 8), groups));
 }
 
 int soft_backward(const uint8_t *frames, const float *dLdm, const uint8_t *gt, long long npx, const float p6[6],

@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import gc
 import heapq
 import time
 
@@ -106,12 +107,24 @@ class Server:
         self.deferred = set()      # sessions that had to wait for a slot
         self.max_waiting = 0
         self.steps = 0
+        self.max_step = 0          # most frames in one step
         self.max_queue = 0
 
     def run(self, sessions, duration, t_max=None, admitted=None):
         """Serves the sessions' frames that arrive before `duration` seconds,
         then drains the queues. `admitted` maps sessions already bound (and
         learned) before the run to their slots. Returns the FrameResults."""
+        # the cyclic garbage collector pauses for tens of milliseconds once many
+        # result objects exist; the loop creates no reference cycles
+        gc_on = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(sessions, duration, t_max, admitted)
+        finally:
+            if gc_on:
+                gc.enable()
+
+    def _run(self, sessions, duration, t_max, admitted):
         be = self.be
         if hasattr(be, "begin"):
             be.begin()
@@ -191,6 +204,7 @@ class Server:
                 inflight[lane] = (be.step(lane, frames), items)
                 busy.update(sid for sid, *_ in items)
                 self.steps += 1
+                self.max_step = max(self.max_step, len(items))
             qlen = sum(len(q) for q in queues.values()) if self.steps % 64 == 0 else 0
             self.max_queue = max(self.max_queue, qlen)
             if t >= duration and not heap and not pending and not waiting and not inflight \

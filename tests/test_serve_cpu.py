@@ -116,7 +116,7 @@ def test_every_frame_served_once_in_order():
     assert all(r.latency >= 0 for r in res)
     assert not srv.deferred
     _check_alone(sessions, res)
-    assert max(be.steps) > 1            # frames of several streams share steps
+    assert max(be.steps) > 1 and srv.max_step == max(be.steps)   # frames of several streams share steps
 
 
 def test_tight_budget_defers_without_dropping():
