@@ -5,18 +5,18 @@ Headline workload (batched form): 64 camera streams whose resolutions are
 drawn by seed from {640x480, 1280x720, 1920x1080, 3840x2160}, each with its
 own learned background, hand path and brightness drift. A step is one frame
 for every stream through the whole per-frame path (gain, classify,
-morphology, components, pointer), launched as one persistent fused kernel
-replayed from a hipGraph. Inputs are resident in HBM before the timed
-region.
+morphology, components, pointer): four kernels replayed from one hipGraph
+(with --autotune, the launch shape the batch's autotuner picks on these
+frames). Inputs are resident in HBM before the timed region.
 
 Also measured, next to it: the plain single-stream form on 1920x1080 frames
 (throughput of process_frames over resident frames, and the latency of
 single-frame calls with the pointer read back on the host).
 
-Printed: one JSON line. `roofline` is the fused step kernel's algorithmic
-bytes per launch over its average duration, taken from the kernel's own
-dispatch events; `cpu_baseline` is the CPU oracle on a bounded sample of the
-same frames.
+Printed: one JSON line. `roofline` is the dominant kernel's (classify's, or
+the fused kernel's in a persistent launch shape) algorithmic bytes per launch
+over its average duration, taken from the kernel's own dispatch events;
+`cpu_baseline` is the CPU oracle on a bounded sample of the same frames.
 """
 import argparse
 import json
@@ -32,6 +32,17 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per pixel of the whole per-frame path: frame 3 +
 # background min/max 6 + reference luminance 2/8 + I_FIZI bits 1/8
 PATH_BYTES_PER_PX = 9.375
+# of the classify kernel: frame 3 + background min/max 6 + raw mask bits 1/8
+CLASSIFY_BYTES_PER_PX = 9.125
+
+
+LAUNCH_NAMES = {0: "four kernels, direct launches", 1: "four kernels replayed from a hipGraph",
+                2: "persistent fused kernel", 3: "persistent fused kernel, hipGraph"}
+
+# measured HBM bytes per launch of the dominant kernel (FETCH_SIZE +
+# WRITE_SIZE, scaled by a plain copy of known size), keyed by kernel; only
+# valid for the kernel code the counters were taken on
+TRAFFIC = {}
 
 
 def log(*a):
@@ -52,6 +63,10 @@ def bench_batched(args, torch, fizi, workloads):
     stream = torch.cuda.current_stream()
 
     b.set_mode(workloads.BATCH_MODE)
+    if args.autotune:
+        best, ms = b.autotune(workloads.step_frames(w, 0), ptrs, steps=5, stream=stream)
+        log(f"autotuned launch shape {best}: {ms:.3f} ms/step")
+    tuning = b.get_tuning()
     for k in range(args.warmup):
         b.step(workloads.step_frames(w, k), ptrs, stream=stream)
     torch.cuda.synchronize()
@@ -76,21 +91,29 @@ def bench_batched(args, torch, fizi, workloads):
         stream.synchronize()
         lat.append((time.perf_counter() - t) * 1e3)
 
-    # the fused kernel's duration from its own dispatch events (same kernel,
-    # launched directly so the events can be attached)
-    b.set_mode(fizi.BATCH_PERSISTENT)
+    # kernel durations from their own dispatch events: the same kernels and
+    # grids, launched directly so that the events can be attached (the
+    # persistent kernel reports its whole launch under "classify")
+    persistent = tuning["mode"] in (fizi.BATCH_PERSISTENT, fizi.BATCH_PERSISTENT_GRAPH)
+    b.set_mode(fizi.BATCH_PERSISTENT if persistent else fizi.BATCH_DIRECT)
     b.stage_timing(True)
     for k in range(args.steps):
         b.step(workloads.step_frames(w, k), ptrs, stream=stream)
     torch.cuda.synchronize()
     st = b.stage_times()
     b.stage_timing(False)
+    b.set_mode(tuning["mode"])
     assert b.status() == 0
+    stages_us = {k: round(v[0] * 1e3 / v[1], 2) for k, v in st.items() if v[1]}
     k_ms, k_n = st["classify"]
     k_avg = k_ms / 1e3 / max(1, k_n)
-    achieved = PATH_BYTES_PER_PX * px / k_avg / 1e9
-    res = dict(w=w, px=px, n=n, sec=sec, lat=lat, k_avg=k_avg, achieved=achieved)
-    return res
+    if persistent:
+        kernel, bpp = "k_step (fused gain, classify, morphology, components)", PATH_BYTES_PER_PX
+    else:
+        kernel, bpp = f"k_classify<{tuning['cls_iters']}> (I_R1, I_R2, I_R3 per pixel)", CLASSIFY_BYTES_PER_PX
+    achieved = bpp * px / k_avg / 1e9
+    return dict(w=w, px=px, n=n, sec=sec, lat=lat, k_avg=k_avg, achieved=achieved, kernel=kernel, bpp=bpp,
+                tuning=tuning, stages_us=stages_us)
 
 
 def bench_plain(args, torch, fizi, scene):
@@ -248,6 +271,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time candidate launch shapes on the workload first and keep the fastest")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device to device 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -302,16 +327,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "batched: 64 streams, resolutions drawn by seed from 640x480, 1280x720, "
                                "1920x1080, 3840x2160, RGB uint8, one frame per stream per step",
-                   "px_per_step": r["px"], "streams": r["n"], "launch": "persistent fused kernel, hipGraph"},
+                   "px_per_step": r["px"], "streams": r["n"], "launch": LAUNCH_NAMES[r["tuning"]["mode"]],
+                   "tuning": r["tuning"]},
         "frames_per_s": round(fps, 1),
         "latency_ms": {"p50": pct(r["lat"], 50), "p99": pct(r["lat"], 99),
                        "mode": "one step of 64 frames submitted, pointers read back on the host"},
         "path_roofline_frac": round(mpxs * 1e6 * PATH_BYTES_PER_PX / (HBM_PEAK_GBS * 1e9), 4),
-        "roofline": {"bound": "hbm", "kernel": "k_step (fused gain, classify, morphology, components)",
+        "roofline": {"bound": "hbm", "kernel": r["kernel"],
                      "achieved": round(r["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(r["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(r["achieved"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(r["kernel"]),
                      "avg_launch_us": round(r["k_avg"] * 1e6, 2),
-                     "bytes_per_launch": int(PATH_BYTES_PER_PX * r["px"])},
+                     "bytes_per_launch": int(r["bpp"] * r["px"])},
+        "stage_us": r["stages_us"],
         "plain_single_stream": plain,
         "serving": serving,
         "soft_mask": soft_res,

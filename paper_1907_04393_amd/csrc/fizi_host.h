@@ -30,7 +30,6 @@ int fail(int code, const std::string &msg);
 constexpr int kMaxW = 8192;
 constexpr int kMaxH = 8192;
 constexpr int kTabSlots = 8;
-constexpr size_t kLdsBudget = 65536;
 constexpr int kTimedLaunches = 16384;
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

@@ -193,28 +193,30 @@ __device__ __forceinline__ void gain_tile(Table *__restrict__ T, int j, int tile
     const int rows = (J->H + J->rs - 1) / J->rs;
     const HueTest h = J->hue;
     uint32_t num = 0, den = 0;
-    for (int rr = tile * kGainRows; rr < min(rows, (tile + 1) * kGainRows); ++rr) {
+    const int r0 = tile * kGainRows, nr = min(rows, r0 + kGainRows) - r0;
+    const int groups = W / 4;
+#pragma unroll 4
+    for (int it = threadIdx.x; it < nr * groups; it += blockDim.x) {
+        const int rr = r0 + it / groups, g = it - (it / groups) * groups;
         const GLOBAL uint32_t *row = G(reinterpret_cast<const uint32_t *>(J->frame + (size_t)rr * J->rs * W * 3));
         const GLOBAL uint64_t *yr = G(reinterpret_cast<const uint64_t *>(J->yref + (size_t)rr * W));
-        for (int g = threadIdx.x; g < W / 4; g += blockDim.x) {
-            const uint32_t w0 = row[3 * g], w1 = row[3 * g + 1], w2 = row[3 * g + 2];
-            const uint64_t yv = yr[g];
+        const uint32_t w0 = row[3 * g], w1 = row[3 * g + 1], w2 = row[3 * g + 2];
+        const uint64_t yv = yr[g];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t r = byte_of(w0, w1, w2, 3 * k), gg = byte_of(w0, w1, w2, 3 * k + 1),
-                               b = byte_of(w0, w1, w2, 3 * k + 2);
-                const uint32_t y = (uint32_t)(yv >> (16 * k)) & 0xFFFFu;
-                bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
-                if (ok) {
-                    const int mx = max(max((int)r, (int)gg), (int)b);
-                    const int mn = min(min((int)r, (int)gg), (int)b);
-                    if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
-                        ok = false;
-                }
-                if (ok) {
-                    num += y;
-                    den += r + 2 * gg + b;
-                }
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = byte_of(w0, w1, w2, 3 * k), gg = byte_of(w0, w1, w2, 3 * k + 1),
+                           b = byte_of(w0, w1, w2, 3 * k + 2);
+            const uint32_t y = (uint32_t)(yv >> (16 * k)) & 0xFFFFu;
+            bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
+            if (ok) {
+                const int mx = max(max((int)r, (int)gg), (int)b);
+                const int mn = min(min((int)r, (int)gg), (int)b);
+                if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
+                    ok = false;
+            }
+            if (ok) {
+                num += y;
+                den += r + 2 * gg + b;
             }
         }
     }
@@ -384,36 +386,15 @@ __device__ __forceinline__ void classify_tile(Table *__restrict__ T, int j, int 
 template <int ITERS>
 __global__ __launch_bounds__(256) void k_classify(Table *__restrict__ T)
 {
-    for_block_tiles(T->h.cls_pre, T->h.njobs, [&](int j, int tile) { classify_tile<ITERS>(T, j, tile, false); });
+    const int nj = T->h.njobs;
+    const int total = T->h.cls_pre[nj];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int j = find_job(T->h.cls_pre, nj, t);
+        classify_tile<ITERS>(T, j, t - T->h.cls_pre[j], false);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive block scan of one uint32 per thread (blockDim.x = 256).
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_wave, uint32_t *total)
-{
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, kWave);
-        if (lane >= o)
-            x += y;
-    }
-    if (lane == kWave - 1)
-        s_wave[wave] = x;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
-        const uint32_t s = s_wave[w];
-        if (w < wave)
-            off += s;
-        tot += s;
-    }
-    __syncthreads();
-    *total = tot;
-    return off + x - v;
-}
-
 // Last pixel (x) of the run of ones that starts at bit b of word w of a row.
 __device__ __forceinline__ int run_end_lds(const uint64_t *row, int Wd, int w, int b)
 {
@@ -430,9 +411,13 @@ __device__ __forceinline__ int run_end_lds(const uint64_t *row, int Wd, int w, i
 }
 
 // A run is packed as (length << 32) | start pixel.
+// A run list entry: start pixel (low word), length (bits 32..62) and the flag
+// kLinkUp (bit 63): the run must still be joined to the row above.
+constexpr uint32_t kLinkUp = 0x80000000u;
+
 __device__ __forceinline__ uint2 unpack_run(uint64_t v)
 {
-    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32) & ~kLinkUp);
 }
 
 // Bit scans of one mask row (W = 64 * Wd pixels).
@@ -543,25 +528,30 @@ __device__ __forceinline__ void link_up(GLOBAL uint32_t *parent, P above, int Wd
 // opening/closing stages held in registers: each stage keeps the two rows
 // before its input, and on input row i emits row i - 1 from the 3x3 window
 // (vertical AND/OR per word, horizontal neighbours from the words' edge bits,
-// exchanged between lanes). Rows outside the image enter a stage as its
-// neutral value (1 for erosion, 0 for dilation), which is exactly the border
-// rule; halo rows inside the image only corrupt rows outside the band. Each
-// final row of the band is stored (I_FIZI), its runs are appended to the
-// frame's run list, and the runs are joined to the touching runs of the row
-// above in a union-find over band-local run indices kept in LDS (indices grow
-// in raster order, so a root is its component's first run in the band).
-// Rows are processed in order, so trees stay shallow. A band with more runs
-// than the LDS table holds falls back to the same union-find in global
-// memory, reading the rows back from I_FIZI.
+// exchanged between neighbouring lanes). Rows outside the image enter a stage
+// as its neutral value (1 for erosion, 0 for dilation), which is exactly the
+// border rule; halo rows inside the image only corrupt rows outside the band.
+// Each final row of the band is stored (I_FIZI) and its runs are joined to the
+// touching runs of the row above in a union-find over segment-local run
+// indices kept in LDS (indices grow in raster order, so a root is its
+// component's first run in the segment). A segment is a stretch of the band's
+// rows whose runs fit the LDS table; when it closes (table full, band done)
+// its runs are appended to the frame's run list with one reservation, each
+// pointing at its segment root. The first run row of a segment that is not the
+// first of the band, and the first row of every band below the top, are
+// flagged: the component stage joins them to the row above. A row with more
+// runs than the table goes to the run list directly, its runs their own roots,
+// flagged, and so is the row after it.
 constexpr int kMaxRowWords = 128;          // W <= 8192
-constexpr int kBandRunsLds = 512;
+constexpr int kSegRuns = 512;              // runs of one LDS segment
 constexpr int kRawChunk = 4;               // rows loaded together (the selects below assume 4)
 
 struct WaveLds {
     uint64_t rows[2][kMaxRowWords];        // the last two final rows
     uint32_t pref[2][kMaxRowWords];        // run starts before each word
-    uint32_t start[kBandRunsLds];          // start pixel of band run k
-    uint32_t par[kBandRunsLds];            // union-find parent (band index)
+    uint32_t start[kSegRuns];              // start pixel of segment run k
+    uint32_t len[kSegRuns];                // its length, kLinkUp if flagged
+    uint32_t par[kSegRuns];                // union-find parent (segment index)
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -570,15 +560,30 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// Lane l receives lane l - 1's value (lane 0 receives 0): DPP wave_shr:1.
+__device__ __forceinline__ uint32_t from_left(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, false);
+}
+
+// Lane l receives lane l + 1's value (lane 63 receives 0): DPP wave_shl:1.
+__device__ __forceinline__ uint32_t from_right(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);
+}
+
+// Inclusive prefix sum over the wave: shifts of 1, 2, 4, 8 inside each row of
+// 16 lanes, then each row's total is carried into the rows above it
+// (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3). Lanes a
+// DPP move does not write keep 0.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o, kWave);
-        if (lane >= o)
-            v += t;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
     return v;
 }
 
@@ -590,14 +595,15 @@ __device__ __forceinline__ void row_carries(const uint64_t *v, int Wd, uint32_t 
 {
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t hi0 = (uint32_t)(v[0] >> 63), lo0 = (uint32_t)v[0] & 1u;
-    const uint32_t up0 = __shfl_up(hi0, 1, kWave), dn0 = __shfl_down(lo0, 1, kWave);
+    const uint32_t up0 = from_left(hi0), dn0 = from_right(lo0);
     lc[0] = lane == 0 ? edge : up0;
     if (NC == 1) {
         rc[0] = (lane + 1 < Wd) ? dn0 : edge;
     } else {
         const uint32_t hi1 = (uint32_t)(v[NC - 1] >> 63), lo1 = (uint32_t)v[NC - 1] & 1u;
-        const uint32_t up1 = __shfl_up(hi1, 1, kWave), dn1 = __shfl_down(lo1, 1, kWave);
-        const uint32_t last_hi0 = __shfl(hi0, kWave - 1, kWave), first_lo1 = __shfl(lo1, 0, kWave);
+        const uint32_t up1 = from_left(hi1), dn1 = from_right(lo1);
+        const uint32_t last_hi0 = (uint32_t)__builtin_amdgcn_readlane((int)hi0, kWave - 1);
+        const uint32_t first_lo1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo1);
         rc[0] = (lane + 1 < Wd) ? (lane == kWave - 1 ? first_lo1 : dn0) : edge;
         lc[NC - 1] = lane == 0 ? last_hi0 : up1;
         rc[NC - 1] = (lane + kWave + 1 < Wd) ? dn1 : edge;
@@ -652,7 +658,7 @@ __device__ __forceinline__ void unite_lds(uint32_t *par, uint32_t a, uint32_t b)
     }
 }
 
-// Band-local index of the run of `row` (LDS) that starts at bit bs.
+// Segment-local index of the run of `row` (LDS) that starts at bit bs.
 __device__ __forceinline__ uint32_t run_index(const uint64_t *row, const uint32_t *pref, uint32_t first, int bs)
 {
     const int w = bs >> 6, b = bs & 63;
@@ -663,6 +669,58 @@ __device__ __forceinline__ uint32_t run_index(const uint64_t *row, const uint32_
 }
 
 __device__ __forceinline__ bool stage_erodes(int k, int oi, int ci) { return (k < oi) || (k >= 2 * oi + ci); }
+
+// Reserves n entries of the frame's run list (one atomic for the wave).
+__device__ __forceinline__ uint32_t reserve_runs(Job *J, uint32_t n, uint32_t cap)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t base = 0;
+    if (lane == 0) {
+        base = atomicAdd(&J->nruns, n);
+        if (base + n > cap)
+            atomicOr(&J->flags, 1u);
+    }
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+}
+
+// Closes a segment: its n runs join the run list, each pointing at its root.
+__device__ __forceinline__ void flush_segment(Job *J, WaveLds &L, uint32_t n, GLOBAL uint64_t *runs,
+                                              GLOBAL uint32_t *parent, GLOBAL uint32_t *area, uint32_t cap)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    if (n == 0)
+        return;
+    const uint32_t base = reserve_runs(J, n, cap);
+    for (uint32_t k = lane; k < n; k += kWave) {
+        const uint32_t st = L.start[k];
+        const uint32_t r = find_lds(L.par, k);
+        if (base + k < cap) {
+            runs[base + k] = ((uint64_t)L.len[k] << 32) | st;
+            st_wg(parent + st, L.start[r]);
+            area[st] = 0u;
+        }
+    }
+    wave_sync();
+}
+
+// Rows r0 .. r0 + kRawChunk - 1 of the raw mask, addresses clamped to rows
+// below yb and words below Wd. Values of clamped rows and words are never
+// used (rows from yb on enter the pipeline as its neutral value, words from Wd
+// on never reach a valid word), so the loads need no condition: they stay in
+// flight while the previous chunk is processed.
+template <int NC>
+__device__ __forceinline__ void load_rows(uint64_t (&dst)[kRawChunk][NC], const GLOBAL uint64_t *raw, int r0, int yb,
+                                          int Wd)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int qq = 0; qq < kRawChunk; ++qq) {
+        const size_t ro = (size_t)min(r0 + qq, yb - 1) * Wd;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            dst[qq][c] = raw[ro + min(lane + kWave * c, Wd - 1)];
+    }
+}
 
 // KMAX: most opening/closing stages a job may have; NC: words per lane.
 template <int KMAX, int NC>
@@ -695,206 +753,172 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
 #pragma unroll
         for (int q = 0; q < NC; ++q)
             p2[k][q] = p1[k][q] = stage_erodes(k, oi, ci) ? ~0ull : 0ull;
-    uint32_t nband = 0, prev_first = 0;
-    bool prev_nonempty = false, over = false;
+    uint32_t nseg = 0, prev_first = 0;
+    bool prev_in_seg = false;   // the previous row has runs in the open segment
+    bool link_next = false;     // the next row joins the row above in the component stage
     const int nsteps = (y1 - ya) + K;
-    uint64_t xb[kRawChunk][NC];
-#pragma unroll 1
-    for (int s = 0; s < nsteps; ++s) {
-        const int q = s & (kRawChunk - 1);
-        if (q == 0) {
-            // the next kRawChunk input rows, loaded together
+    // one input row through the stages, then the band's final row it yields
+    auto step = [&](int s, int q, const uint64_t (&ch)[kRawChunk][NC]) __attribute__((always_inline)) {
+        uint64_t x[NC];
+        const bool past = ya + s >= yb;
+        const uint64_t n0 = (K > 0 && stage_erodes(0, oi, ci)) ? ~0ull : 0ull;
 #pragma unroll
-            for (int qq = 0; qq < kRawChunk; ++qq) {
-                const int r = ya + s + qq;
-#pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    xb[qq][c] = (r < yb && valid_w[c]) ? raw[(size_t)r * Wd + lane + kWave * c] : 0ull;
-            }
+        for (int c = 0; c < NC; ++c) {
+            const uint64_t v = q == 0 ? ch[0][c] : (q == 1 ? ch[1][c] : (q == 2 ? ch[2][c] : ch[3][c]));
+            x[c] = past ? n0 : v;
         }
-        {
-            uint64_t x[NC];
-            const bool past = ya + s >= yb;
-            const uint64_t n0 = (K > 0 && stage_erodes(0, oi, ci)) ? ~0ull : 0ull;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const uint64_t v = q == 0 ? xb[0][c] : (q == 1 ? xb[1][c] : (q == 2 ? xb[2][c] : xb[3][c]));
-                x[c] = past ? n0 : v;
-            }
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                if (k < K) {
-                    const bool ero = stage_erodes(k, oi, ci);
-                    const int i = ya + s - k;
-                    if (i < 0 || i >= H) {
-#pragma unroll
-                        for (int c = 0; c < NC; ++c)
-                            x[c] = ero ? ~0ull : 0ull;
-                    }
-                    uint64_t o[NC];
-                    morph_row<NC>(ero, p2[k], p1[k], x, Wd, o);
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        p2[k][c] = p1[k][c];
-                        p1[k][c] = x[c];
-                    }
-                    const int jr = i - 1;
-                    const bool oob = k + 1 < K && (jr < 0 || jr >= H);
-                    const uint64_t n1 = stage_erodes(k + 1, oi, ci) ? ~0ull : 0ull;
+        for (int k = 0; k < KMAX; ++k) {
+            if (k < K) {
+                const bool ero = stage_erodes(k, oi, ci);
+                const int i = ya + s - k;
+                if (i < 0 || i >= H) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c)
-                        x[c] = oob ? n1 : o[c];
+                        x[c] = ero ? ~0ull : 0ull;
+                }
+                uint64_t o[NC];
+                morph_row<NC>(ero, p2[k], p1[k], x, Wd, o);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    p2[k][c] = p1[k][c];
+                    p1[k][c] = x[c];
+                }
+                const int jr = i - 1;
+                const bool oob = k + 1 < K && (jr < 0 || jr >= H);
+                const uint64_t n1 = stage_erodes(k + 1, oi, ci) ? ~0ull : 0ull;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    x[c] = oob ? n1 : o[c];
+            }
+        }
+        const int jrow = ya + s - K;
+        if (jrow < y0 || jrow >= y1)
+            return;
+        // a final I_FIZI row
+        GLOBAL uint64_t *frow = fz + (size_t)jrow * Wd;
+        uint64_t orw = 0ull;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (valid_w[c])
+                frow[lane + kWave * c] = x[c];
+            else
+                x[c] = 0ull;
+            orw |= x[c];
+        }
+        if (__ballot(orw != 0ull) == 0ull) {
+            prev_in_seg = false;
+            link_next = false;
+            return;
+        }
+        const int cur = (jrow - y0) & 1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (valid_w[c])
+                L.rows[cur][lane + kWave * c] = x[c];
+        uint32_t lcs[NC], rcs[NC];
+        row_carries<NC>(x, Wd, 0u, lcs, rcs);
+        uint64_t st[NC];
+        uint32_t ex[NC];
+        uint32_t total = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            st[c] = x[c] & ~((x[c] << 1) | lcs[c]);
+            const uint32_t n = (uint32_t)__popcll(st[c]);
+            const uint32_t inc = wave_incl_scan(n);
+            ex[c] = total + inc - n;
+            total += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+            if (valid_w[c])
+                L.pref[cur][lane + kWave * c] = ex[c];
+        }
+        wave_sync();
+        bool up = (jrow == y0 && y0 > 0) || link_next;
+        link_next = false;
+        if (nseg + total > (uint32_t)kSegRuns) {
+            // the open segment is full: close it, this row opens the next
+            flush_segment(J, L, nseg, runs, parent, area, cap);
+            up = up || prev_in_seg;
+            nseg = 0;
+            prev_in_seg = false;
+        }
+        const bool direct = total > (uint32_t)kSegRuns;
+        const uint32_t base = direct ? reserve_runs(J, total, cap) : 0u;
+        const uint32_t flag = up ? kLinkUp : 0u;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            uint64_t m = st[c];
+            const int w = lane + kWave * c;
+            while (m) {
+                const int b = __builtin_ctzll(m);
+                const uint32_t k = ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
+                m &= m - 1;
+                const int xs = 64 * w + b;
+                const int xe = run_end_lds(L.rows[cur], Wd, w, b);
+                const uint32_t start = (uint32_t)jrow * (uint32_t)W + (uint32_t)xs;
+                const uint32_t len = (uint32_t)(xe - xs + 1) | flag;
+                if (!direct) {
+                    L.start[nseg + k] = start;
+                    L.len[nseg + k] = len;
+                    L.par[nseg + k] = nseg + k;
+                } else if (base + k < cap) {
+                    runs[base + k] = ((uint64_t)len << 32) | start;
+                    st_wg(parent + start, start);
+                    area[start] = 0u;
                 }
             }
-            const int jrow = ya + s - K;
-            if (jrow < y0 || jrow >= y1)
-                continue;
-            // a final I_FIZI row
-            GLOBAL uint64_t *frow = fz + (size_t)jrow * Wd;
-            uint64_t orw = 0ull;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if (valid_w[c])
-                    frow[lane + kWave * c] = x[c];
-                else
-                    x[c] = 0ull;
-                orw |= x[c];
-            }
-            if (__ballot(orw != 0ull) == 0ull) {
-                prev_nonempty = false;
-                continue;
-            }
-            const int cur = (jrow - y0) & 1;
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-                if (valid_w[c])
-                    L.rows[cur][lane + kWave * c] = x[c];
-            uint32_t lcs[NC], rcs[NC];
-            row_carries<NC>(x, Wd, 0u, lcs, rcs);
-            uint64_t st[NC];
-            uint32_t ex[NC];
-            uint32_t total = 0;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                st[c] = x[c] & ~((x[c] << 1) | lcs[c]);
-                const uint32_t n = (uint32_t)__popcll(st[c]);
-                const uint32_t inc = wave_incl_scan(n);
-                ex[c] = total + inc - n;
-                total += __shfl(inc, kWave - 1, kWave);
-                if (valid_w[c])
-                    L.pref[cur][lane + kWave * c] = ex[c];
-            }
-            uint32_t gbase = 0;
-            if (lane == 0)
-                gbase = atomicAdd(&J->nruns, total);
-            gbase = __shfl(gbase, 0, kWave);
-            if (lane == 0 && gbase + total > cap)
-                atomicOr(&J->flags, 1u);
-            wave_sync();
-            const bool use_lds = !over && nband + total <= (uint32_t)kBandRunsLds;
-            // emit the row's runs
+        }
+        wave_sync();
+        if (direct) {
+            link_next = true;
+            return;
+        }
+        // join with the touching runs of the row above (same segment)
+        if (prev_in_seg) {
+            const int prv = cur ^ 1;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 uint64_t m = st[c];
                 const int w = lane + kWave * c;
                 while (m) {
                     const int b = __builtin_ctzll(m);
-                    const uint32_t k = ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
+                    const uint32_t k = nseg + ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
                     m &= m - 1;
                     const int xs = 64 * w + b;
                     const int xe = run_end_lds(L.rows[cur], Wd, w, b);
-                    const uint32_t start = (uint32_t)jrow * (uint32_t)W + (uint32_t)xs;
-                    if (gbase + k < cap) {
-                        runs[gbase + k] = ((uint64_t)(uint32_t)(xe - xs + 1) << 32) | start;
-                        st_wg(parent + start, start);
-                        area[start] = 0u;
-                    }
-                    if (use_lds) {
-                        L.start[nband + k] = start;
-                        L.par[nband + k] = nband + k;
+                    const int hi = min(xe + 1, W - 1);
+                    int pos = max(xs - 1, 0);
+                    while (pos <= hi) {
+                        const int xb2 = next_one(L.rows[prv], pos, hi);
+                        if (xb2 < 0)
+                            break;
+                        const int bs = prev_zero(L.rows[prv], xb2) + 1;
+                        unite_lds(L.par, k, run_index(L.rows[prv], L.pref[prv], prev_first, bs));
+                        pos = next_zero(L.rows[prv], Wd, xb2) + 1;
                     }
                 }
             }
             wave_sync();
-            // join with the touching runs of the row above (same band)
-            if (use_lds && prev_nonempty && jrow > y0) {
-                const int prv = cur ^ 1;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    uint64_t m = st[c];
-                    const int w = lane + kWave * c;
-                    while (m) {
-                        const int b = __builtin_ctzll(m);
-                        const uint32_t k = nband + ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
-                        m &= m - 1;
-                        const int xs = 64 * w + b;
-                        const int xe = run_end_lds(L.rows[cur], Wd, w, b);
-                        const int hi = min(xe + 1, W - 1);
-                        int pos = max(xs - 1, 0);
-                        while (pos <= hi) {
-                            const int xb2 = next_one(L.rows[prv], pos, hi);
-                            if (xb2 < 0)
-                                break;
-                            const int bs = prev_zero(L.rows[prv], xb2) + 1;
-                            unite_lds(L.par, k, run_index(L.rows[prv], L.pref[prv], prev_first, bs));
-                            pos = next_zero(L.rows[prv], Wd, xb2) + 1;
-                        }
-                    }
-                }
-                wave_sync();
-            }
-            if (!use_lds)
-                over = true;
-            prev_first = nband;
-            nband += total;
-            prev_nonempty = true;
         }
+        prev_first = nseg;
+        nseg += total;
+        prev_in_seg = true;
+    };
+    // input chunks alternate between two register buffers: each is loaded a
+    // chunk ahead of its use, straight into the registers that use it
+    uint64_t ca[kRawChunk][NC], cb[kRawChunk][NC];
+    load_rows<NC>(ca, raw, ya, yb, Wd);
+#pragma unroll 1
+    for (int s0 = 0; s0 < nsteps; s0 += 2 * kRawChunk) {
+        load_rows<NC>(cb, raw, ya + s0 + kRawChunk, yb, Wd);
+#pragma unroll 1
+        for (int q = 0; q < kRawChunk && s0 + q < nsteps; ++q)
+            step(s0 + q, q, ca);
+        load_rows<NC>(ca, raw, ya + s0 + 2 * kRawChunk, yb, Wd);
+#pragma unroll 1
+        for (int q = 0; q < kRawChunk && s0 + kRawChunk + q < nsteps; ++q)
+            step(s0 + kRawChunk + q, q, cb);
     }
-    if (!over) {
-        // every run of the band points at the band root's start pixel
-        for (uint32_t k = lane; k < nband; k += kWave) {
-            const uint32_t r = find_lds(L.par, k);
-            if (r != k)
-                st_wg(parent + L.start[k], L.start[r]);
-        }
-        return;
-    }
-    // too many runs for LDS: the same union-find over the band in global memory
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    for (int jr = y0 + 1; jr < y1; ++jr) {
-        const GLOBAL uint64_t *row = fz + (size_t)jr * Wd;
-        for (int w = lane; w < Wd; w += kWave) {
-            const uint64_t word = row[w];
-            const uint64_t prev = w > 0 ? row[w - 1] : 0ull;
-            uint64_t m = word & ~((word << 1) | (prev >> 63));
-            while (m) {
-                const int b = __builtin_ctzll(m);
-                m &= m - 1;
-                const int xs = 64 * w + b;
-                int xe = xs;
-                while (xe + 1 < W && ((row[(xe + 1) >> 6] >> ((xe + 1) & 63)) & 1ull))
-                    ++xe;
-                link_up(parent, row - Wd, Wd, W, jr, xs, xe, (uint32_t)jr * (uint32_t)W + (uint32_t)xs);
-            }
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    for (int jr = y0; jr < y1; ++jr) {
-        const GLOBAL uint64_t *row = fz + (size_t)jr * Wd;
-        for (int w = lane; w < Wd; w += kWave) {
-            const uint64_t word = row[w];
-            const uint64_t prev = w > 0 ? row[w - 1] : 0ull;
-            uint64_t m = word & ~((word << 1) | (prev >> 63));
-            while (m) {
-                const int b = __builtin_ctzll(m);
-                m &= m - 1;
-                const uint32_t start = (uint32_t)jr * (uint32_t)W + (uint32_t)(64 * w + b);
-                const uint32_t root = find_root(parent, start);
-                if (root != start)
-                    st_wg(parent + start, root);
-            }
-        }
-    }
+    flush_segment(J, L, nseg, runs, parent, area, cap);
 }
 
 template <int KMAX, int NC>
@@ -941,7 +965,7 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
     __shared__ unsigned long long s_u64[kMaxWaves];
     __shared__ uint32_t s_u32[kMaxWaves];
     Job *J = &T->jobs[j];
-    const int W = J->W, H = J->H, Wd = J->Wd, band = J->band;
+    const int W = J->W, H = J->H, Wd = J->Wd;
     const uint32_t nr = min(ld_dev(&J->nruns), J->run_cap);
     const GLOBAL uint64_t *runs = G(reinterpret_cast<const uint64_t *>(J->runs));
     GLOBAL uint32_t *parent = G(J->parent);
@@ -952,11 +976,14 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
     if (hand)
         for (int i = threadIdx.x; i < H * Wd; i += blockDim.x)
             hand[i] = 0ull;
-    // A: runs on the first row of a band join the band above
+    // A: flagged runs (first rows of bands and segments) join the row above
     for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
-        const uint2 rn = unpack_run(runs[i]);
+        const uint64_t rv = runs[i];
+        if (!((uint32_t)(rv >> 32) & kLinkUp))
+            continue;
+        const uint2 rn = unpack_run(rv);
         const int y = (int)(rn.x / (uint32_t)W);
-        if (y == 0 || y % band != 0)
+        if (y == 0)
             continue;
         const int xs = (int)(rn.x - (uint32_t)y * W), xe = xs + (int)rn.y - 1;
         link_up(parent, fz + (size_t)(y - 1) * Wd, Wd, W, y, xs, xe, rn.x);
@@ -1099,7 +1126,10 @@ __global__ __launch_bounds__(256) void k_step(Table *__restrict__ T, PersistStat
     for_block_tiles(T->h.gain_pre, nj, [&](int j, int tile) { gain_tile(T, j, tile); });
     bool ok = grid_sync(ps, 1);
     if (ok)
-        for_block_tiles(T->h.cls_pre, nj, [&](int j, int tile) { classify_tile<ITERS>(T, j, tile, true); });
+        for (int t = blockIdx.x; t < T->h.cls_pre[nj]; t += gridDim.x) {
+            const int j = find_job(T->h.cls_pre, nj, t);
+            classify_tile<ITERS>(T, j, t - T->h.cls_pre[j], true);
+        }
     ok = grid_sync(ps, 2) && ok;
     if (ok) {
         __shared__ WaveLds s_wl[256 / kWave];

@@ -13,7 +13,7 @@ import torch
 from . import fizi, scene
 
 # launch configuration of the multi-stream benchmark
-BATCH_MODE = fizi.BATCH_PERSISTENT_GRAPH
+BATCH_MODE = fizi.BATCH_GRAPH
 
 
 def batched(n_streams=64, pool=4, n_bg=30, device="cuda", seed=2, log=None):

@@ -217,3 +217,42 @@ def test_autotune_keeps_results():
     _same(_run_steps(b, hands, specs, 2, dev), ref)
     with pytest.raises(fizi.FiziError):
         b.set_tuning(cls_iters=3)
+
+
+def test_dense_masks_every_band_height():
+    """Dense run masks (segment seams, rows of over 512 runs) at every band
+    height and in the direct and persistent launch modes."""
+    from test_gpu_plain import dense_frames
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    cases = [(2048, 40, "mixed"), (640, 64, "noise"), (2048, 24, "checker")]
+    prm = dict(open_iters=0, close_iters=0)
+    data = [dense_frames(W, H, k) for W, H, k in cases]
+    orc = []
+    from oracle import oracle
+    for (W, H, _), (bg, hand) in zip(cases, data):
+        m = oracle.Model(W, H, oracle.params(**prm))
+        m.learn(bg.numpy())
+        orc.append([m.process(hand[k].numpy(), frame_index=k) for k in range(hand.shape[0])])
+    b = fizi.Batch([(W, H) for W, H, _ in cases], [fizi.default_params(**prm)] * len(cases), device=dev)
+    for i, (bg, _) in enumerate(data):
+        b.learn(i, bg.to(dev))
+    hands = [h.to(dev) for _, h in data]
+    for mode in (0, 2):
+        for rows in (8, 16, 32, 64):
+            print("dense batch mode", mode, "rows", rows, flush=True)
+            b.set_tuning(mode=mode, cls_iters=4, morph_rows=rows, grid_per_cu=8)
+            for k in range(2):
+                ptrs = torch.empty((len(cases), 56), dtype=torch.uint8, device=dev)
+                fz = [torch.empty((H, W // 64), dtype=torch.int64, device=dev) for W, H, _ in cases]
+                b.step([h[k] for h in hands], ptrs, fizi=fz)
+                torch.cuda.synchronize()
+                got = fizi.pointers_to_numpy(ptrs)
+                for i, (W, H, kind) in enumerate(cases):
+                    p = fizi.pointer_dict(got[i])
+                    ref = dict(orc[i][k]["pointer"])
+                    p.pop("frame_index"), ref.pop("frame_index")
+                    assert p == ref, (mode, rows, k, kind)
+                    assert np.array_equal(fizi.unpack_bits(fz[i], W), orc[i][k]["fizi"]), (mode, rows, k, kind)
+            assert b.status() == 0
+    b.close()

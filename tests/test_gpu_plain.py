@@ -135,6 +135,48 @@ def test_degenerate_frames():
     assert outs[0]["pointer"]["present"] == 0
 
 
+def dense_pattern(W, H, kind, seed):
+    """Foreground patterns with many runs per row: a one-pixel checkerboard
+    (one 8-connected component), one-pixel stripes, 50% noise, and a mix of
+    noise, checkerboard rows and full rows."""
+    g = torch.Generator().manual_seed(seed)
+    yy, xx = torch.meshgrid(torch.arange(H), torch.arange(W), indexing="ij")
+    if kind == "checker":
+        return (yy + xx) % 2 == 0
+    if kind == "stripes":
+        return (xx % 2 == 0).expand(H, W)
+    if kind == "noise":
+        return torch.rand((H, W), generator=g) < 0.5
+    m = torch.rand((H, W), generator=g) < 0.3
+    m |= ((yy % 7) < 2) & ((yy + xx) % 2 == 0)
+    m |= (yy % 11) == 5
+    return m
+
+
+def dense_frames(W, H, kind, n=2):
+    bg = torch.full((2, H, W, 3), 40, dtype=torch.uint8)
+    bg[..., 2] = 90
+    skin = torch.tensor([210, 140, 90], dtype=torch.uint8)
+    hand = bg[:1].repeat(n, 1, 1, 1)
+    for k in range(n):
+        hand[k][dense_pattern(W, H, kind, k)] = skin
+    return bg, hand
+
+
+@pytest.mark.parametrize("W,H,kind", [(2048, 40, "checker"), (2048, 24, "stripes"), (640, 64, "noise"),
+                                      (1088, 50, "mixed"), (128, 70, "checker")])
+def test_dense_run_masks(W, H, kind):
+    """More runs than a band's LDS segment table holds: segments close every
+    few rows, rows of over 512 runs go to the run list directly, and
+    components must join across every such seam."""
+    bg, hand = dense_frames(W, H, kind)
+    for params in ({}, dict(open_iters=0, close_iters=0)):
+        print("dense", W, H, kind, params, flush=True)
+        g = gpu_run(bg, hand, params, chunk=2)
+        m, outs = oracle_run(bg, hand, params)
+        compare(g, m, outs, f"dense {kind} {params}")
+
+
 def test_hue_gray_all_2e24_colours():
     """Every RGB triple once (a 4096x4096 frame), gain pinned to 1, a
     background point-box that every colour leaves, no morphology: I_FIZI is
