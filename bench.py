@@ -39,10 +39,11 @@ CLASSIFY_BYTES_PER_PX = 9.125
 LAUNCH_NAMES = {0: "four kernels, direct launches", 1: "four kernels replayed from a hipGraph",
                 2: "persistent fused kernel", 3: "persistent fused kernel, hipGraph"}
 
-# measured HBM bytes per launch of the dominant kernel (FETCH_SIZE +
-# WRITE_SIZE, scaled by a plain copy of known size), keyed by kernel; only
-# valid for the kernel code the counters were taken on
-TRAFFIC = {}
+# measured HBM bytes per launch of the dominant kernel on this workload:
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB -> 1 GiB
+# elementwise kernel gives), keyed by kernel; valid only for the kernel code
+# the counters were taken on
+TRAFFIC = {"k_classify<4> (I_R1, I_R2, I_R3 per pixel)": 1719.2e6}
 
 
 def log(*a):
@@ -274,7 +275,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time candidate launch shapes on the workload first and keep the fastest")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="first copy 1 GiB device to device 3 times (reference for HBM counters)")
+                    help="first run a 1 GiB -> 1 GiB elementwise kernel 3 times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (the pipeline has no multi-GPU path); "
@@ -285,10 +286,12 @@ def main():
     from paper_1907_04393_amd import fizi, scene, workloads
 
     if args.copy_probe:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        # a plain streaming kernel of known traffic (1 GiB read, 1 GiB
+        # written per launch) to scale the HBM byte counters by
+        a = torch.zeros(1 << 28, dtype=torch.int32, device="cuda:0")
         c = torch.empty_like(a)
         for _ in range(3):
-            c.copy_(a)
+            torch.neg(a, out=c)
         torch.cuda.synchronize()
         del a, c
     r = bench_batched(args, torch, fizi, workloads)
