@@ -395,29 +395,16 @@ __global__ __launch_bounds__(256) void k_classify(Table *__restrict__ T)
 }
 
 // ---------------------------------------------------------------------------
-// Last pixel (x) of the run of ones that starts at bit b of word w of a row.
-__device__ __forceinline__ int run_end_lds(const uint64_t *row, int Wd, int w, int b)
-{
-    uint64_t word = row[w];
-    uint64_t nxt = (w + 1 < Wd) ? row[w + 1] : 0ull;
-    uint64_t ends = (word & ~((word >> 1) | (nxt << 63))) & (~0ull << b);
-    while (!ends) {
-        ++w;
-        word = row[w];
-        nxt = (w + 1 < Wd) ? row[w + 1] : 0ull;
-        ends = word & ~((word >> 1) | (nxt << 63));
-    }
-    return 64 * w + __builtin_ctzll(ends);
-}
-
 // A run is packed as (length << 32) | start pixel.
-// A run list entry: start pixel (low word), length (bits 32..62) and the flag
-// kLinkUp (bit 63): the run must still be joined to the row above.
+// A run list entry: first pixel (low word), last pixel (bits 32..62) and the
+// flag kLinkUp (bit 63): the run must still be joined to the row above.
 constexpr uint32_t kLinkUp = 0x80000000u;
 
+// (first pixel, length) of a run list entry
 __device__ __forceinline__ uint2 unpack_run(uint64_t v)
 {
-    return make_uint2((uint32_t)v, (uint32_t)(v >> 32) & ~kLinkUp);
+    const uint32_t a = (uint32_t)v, e = (uint32_t)(v >> 32) & ~kLinkUp;
+    return make_uint2(a, e - a + 1u);
 }
 
 // Bit scans of one mask row (W = 64 * Wd pixels).
@@ -531,26 +518,26 @@ __device__ __forceinline__ void link_up(GLOBAL uint32_t *parent, P above, int Wd
 // exchanged between neighbouring lanes). Rows outside the image enter a stage
 // as its neutral value (1 for erosion, 0 for dilation), which is exactly the
 // border rule; halo rows inside the image only corrupt rows outside the band.
-// Each final row of the band is stored (I_FIZI) and its runs are joined to the
-// touching runs of the row above in a union-find over segment-local run
-// indices kept in LDS (indices grow in raster order, so a root is its
-// component's first run in the segment). A segment is a stretch of the band's
-// rows whose runs fit the LDS table; when it closes (table full, band done)
-// its runs are appended to the frame's run list with one reservation, each
-// pointing at its segment root. The first run row of a segment that is not the
-// first of the band, and the first row of every band below the top, are
-// flagged: the component stage joins them to the row above. A row with more
-// runs than the table goes to the run list directly, its runs their own roots,
-// flagged, and so is the row after it.
+// Each final row of the band is stored (I_FIZI); its run starts and ends are
+// bit masks of each lane's word, numbered by a wave prefix sum, so the lanes
+// holding a run's first and last pixel write them without scanning. Runs are
+// joined to the touching runs of the row above (kept in registers) in a
+// union-find over segment-local run indices kept in LDS (indices grow in
+// raster order, so a root is its component's first run in the segment). A
+// segment is a stretch of the band's rows whose runs fit the LDS table; when
+// it closes (table full, band done) its runs are appended to the frame's run
+// list with one reservation, each pointing at its segment root. The first run
+// row of a segment that is not the first of the band, and the first row of
+// every band below the top, are flagged: the component stage joins them to the
+// row above. A row with more runs than the table goes to the run list
+// directly, its runs their own roots, flagged, and so is the row after it.
 constexpr int kMaxRowWords = 128;          // W <= 8192
 constexpr int kSegRuns = 512;              // runs of one LDS segment
 constexpr int kRawChunk = 4;               // rows loaded together (the selects below assume 4)
 
 struct WaveLds {
-    uint64_t rows[2][kMaxRowWords];        // the last two final rows
-    uint32_t pref[2][kMaxRowWords];        // run starts before each word
-    uint32_t start[kSegRuns];              // start pixel of segment run k
-    uint32_t len[kSegRuns];                // its length, kLinkUp if flagged
+    uint32_t start[kSegRuns];              // first pixel of segment run k
+    uint32_t end[kSegRuns];                // its last pixel, | kLinkUp if flagged
     uint32_t par[kSegRuns];                // union-find parent (segment index)
 };
 
@@ -658,14 +645,23 @@ __device__ __forceinline__ void unite_lds(uint32_t *par, uint32_t a, uint32_t b)
     }
 }
 
-// Segment-local index of the run of `row` (LDS) that starts at bit bs.
-__device__ __forceinline__ uint32_t run_index(const uint64_t *row, const uint32_t *pref, uint32_t first, int bs)
+// Bit t of a row around this lane's word w, t in [-1, 64]: -1 is the last
+// bit of the word on the left (lc), 64 the first bit of the word on the right
+// (rc).
+__device__ __forceinline__ uint32_t bit_at(int t, uint64_t w, uint32_t lc, uint32_t rc)
 {
-    const int w = bs >> 6, b = bs & 63;
-    const uint64_t word = row[w];
-    const uint64_t prev = w > 0 ? row[w - 1] : 0ull;
-    const uint64_t st = word & ~((word << 1) | (prev >> 63));
-    return first + pref[w] + (uint32_t)__popcll(st & ((1ull << b) - 1ull));
+    return t < 0 ? lc : (t > 63 ? rc : (uint32_t)(w >> t) & 1u);
+}
+
+// Row-local index of the run that contains bit t (set, t in [-1, 64]) around
+// this lane's word w, whose run starts are st, with ex runs starting before it.
+__device__ __forceinline__ uint32_t run_at(int t, uint32_t ex, uint64_t st, uint64_t w, uint32_t rc)
+{
+    if (t < 0)
+        return ex - 1u;
+    if (t > 63)
+        return ex + (uint32_t)__popcll(st) + (rc & ~(uint32_t)(w >> 63) & 1u) - 1u;
+    return ex + (uint32_t)__popcll(st & (~0ull >> (63 - t))) - 1u;
 }
 
 __device__ __forceinline__ bool stage_erodes(int k, int oi, int ci) { return (k < oi) || (k >= 2 * oi + ci); }
@@ -695,7 +691,7 @@ __device__ __forceinline__ void flush_segment(Job *J, WaveLds &L, uint32_t n, GL
         const uint32_t st = L.start[k];
         const uint32_t r = find_lds(L.par, k);
         if (base + k < cap) {
-            runs[base + k] = ((uint64_t)L.len[k] << 32) | st;
+            runs[base + k] = ((uint64_t)L.end[k] << 32) | st;
             st_wg(parent + st, L.start[r]);
             area[st] = 0u;
         }
@@ -756,6 +752,14 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
     uint32_t nseg = 0, prev_first = 0;
     bool prev_in_seg = false;   // the previous row has runs in the open segment
     bool link_next = false;     // the next row joins the row above in the component stage
+    // the previous final row: words, edge carries, run starts, runs before each word
+    uint64_t pw[NC], pst[NC];
+    uint32_t plc[NC], prc[NC], pex[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        pw[c] = pst[c] = 0ull;
+        plc[c] = prc[c] = pex[c] = 0u;
+    }
     const int nsteps = (y1 - ya) + K;
     // one input row through the stages, then the band's final row it yields
     auto step = [&](int s, int q, const uint64_t (&ch)[kRawChunk][NC]) __attribute__((always_inline)) {
@@ -811,27 +815,20 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
             link_next = false;
             return;
         }
-        const int cur = (jrow - y0) & 1;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (valid_w[c])
-                L.rows[cur][lane + kWave * c] = x[c];
         uint32_t lcs[NC], rcs[NC];
         row_carries<NC>(x, Wd, 0u, lcs, rcs);
-        uint64_t st[NC];
+        uint64_t st[NC], en[NC];
         uint32_t ex[NC];
         uint32_t total = 0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             st[c] = x[c] & ~((x[c] << 1) | lcs[c]);
+            en[c] = x[c] & ~((x[c] >> 1) | ((uint64_t)rcs[c] << 63));
             const uint32_t n = (uint32_t)__popcll(st[c]);
             const uint32_t inc = wave_incl_scan(n);
             ex[c] = total + inc - n;
             total += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
-            if (valid_w[c])
-                L.pref[cur][lane + kWave * c] = ex[c];
         }
-        wave_sync();
         bool up = (jrow == y0 && y0 > 0) || link_next;
         link_next = false;
         if (nseg + total > (uint32_t)kSegRuns) {
@@ -844,27 +841,38 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
         const bool direct = total > (uint32_t)kSegRuns;
         const uint32_t base = direct ? reserve_runs(J, total, cap) : 0u;
         const uint32_t flag = up ? kLinkUp : 0u;
+        const uint32_t rowpx = (uint32_t)jrow * (uint32_t)W;
+        GLOBAL uint32_t *runw = reinterpret_cast<GLOBAL uint32_t *>(runs);
+        // record the row's runs: the lane holding a run's first pixel writes
+        // its start, the lane holding its last pixel its end
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
+            const uint32_t wpx = rowpx + 64u * (uint32_t)(lane + kWave * c);
             uint64_t m = st[c];
-            const int w = lane + kWave * c;
             while (m) {
                 const int b = __builtin_ctzll(m);
                 const uint32_t k = ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
                 m &= m - 1;
-                const int xs = 64 * w + b;
-                const int xe = run_end_lds(L.rows[cur], Wd, w, b);
-                const uint32_t start = (uint32_t)jrow * (uint32_t)W + (uint32_t)xs;
-                const uint32_t len = (uint32_t)(xe - xs + 1) | flag;
+                const uint32_t start = wpx + (uint32_t)b;
                 if (!direct) {
                     L.start[nseg + k] = start;
-                    L.len[nseg + k] = len;
                     L.par[nseg + k] = nseg + k;
                 } else if (base + k < cap) {
-                    runs[base + k] = ((uint64_t)len << 32) | start;
+                    runw[2 * (size_t)(base + k)] = start;
                     st_wg(parent + start, start);
                     area[start] = 0u;
                 }
+            }
+            m = en[c];
+            while (m) {
+                const int e = __builtin_ctzll(m);
+                const uint32_t k = ex[c] + (uint32_t)__popcll(st[c] & (~0ull >> (63 - e))) - 1u;
+                m &= m - 1;
+                const uint32_t end = (wpx + (uint32_t)e) | flag;
+                if (!direct)
+                    L.end[nseg + k] = end;
+                else if (base + k < cap)
+                    runw[2 * (size_t)(base + k) + 1] = end;
             }
         }
         wave_sync();
@@ -872,32 +880,52 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
             link_next = true;
             return;
         }
-        // join with the touching runs of the row above (same segment)
+        // join with the touching runs of the row above (same segment). Two
+        // runs of consecutive rows touch under 8-connectivity exactly when
+        // one's first pixel has a pixel of the other within one column, so
+        // each run start looks at the three pixels above (or below) it.
         if (prev_in_seg) {
-            const int prv = cur ^ 1;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 uint64_t m = st[c];
-                const int w = lane + kWave * c;
                 while (m) {
                     const int b = __builtin_ctzll(m);
                     const uint32_t k = nseg + ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
                     m &= m - 1;
-                    const int xs = 64 * w + b;
-                    const int xe = run_end_lds(L.rows[cur], Wd, w, b);
-                    const int hi = min(xe + 1, W - 1);
-                    int pos = max(xs - 1, 0);
-                    while (pos <= hi) {
-                        const int xb2 = next_one(L.rows[prv], pos, hi);
-                        if (xb2 < 0)
-                            break;
-                        const int bs = prev_zero(L.rows[prv], xb2) + 1;
-                        unite_lds(L.par, k, run_index(L.rows[prv], L.pref[prv], prev_first, bs));
-                        pos = next_zero(L.rows[prv], Wd, xb2) + 1;
+                    if (bit_at(b, pw[c], plc[c], prc[c])) {
+                        unite_lds(L.par, k, prev_first + run_at(b, pex[c], pst[c], pw[c], prc[c]));
+                    } else {
+                        if (bit_at(b - 1, pw[c], plc[c], prc[c]))
+                            unite_lds(L.par, k, prev_first + run_at(b - 1, pex[c], pst[c], pw[c], prc[c]));
+                        if (bit_at(b + 1, pw[c], plc[c], prc[c]))
+                            unite_lds(L.par, k, prev_first + run_at(b + 1, pex[c], pst[c], pw[c], prc[c]));
+                    }
+                }
+                m = pst[c];
+                while (m) {
+                    const int b = __builtin_ctzll(m);
+                    const uint32_t k = prev_first + pex[c] + (uint32_t)__popcll(pst[c] & ((1ull << b) - 1ull));
+                    m &= m - 1;
+                    if (bit_at(b, x[c], lcs[c], rcs[c])) {
+                        unite_lds(L.par, k, nseg + run_at(b, ex[c], st[c], x[c], rcs[c]));
+                    } else {
+                        if (bit_at(b - 1, x[c], lcs[c], rcs[c]))
+                            unite_lds(L.par, k, nseg + run_at(b - 1, ex[c], st[c], x[c], rcs[c]));
+                        if (bit_at(b + 1, x[c], lcs[c], rcs[c]))
+                            unite_lds(L.par, k, nseg + run_at(b + 1, ex[c], st[c], x[c], rcs[c]));
                     }
                 }
             }
             wave_sync();
+        }
+        // this row becomes the row above
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            pw[c] = x[c];
+            pst[c] = st[c];
+            plc[c] = lcs[c];
+            prc[c] = rcs[c];
+            pex[c] = ex[c];
         }
         prev_first = nseg;
         nseg += total;
