@@ -62,7 +62,8 @@ struct Slot {
     uint32_t *parent = nullptr;
     uint32_t *area = nullptr;
     uint2 *runs = nullptr;
-    uint32_t run_cap = 0;
+    uint2 *links = nullptr;
+    uint32_t run_cap = 0, link_cap = 0;
 };
 size_t slot_bytes(const fizi_geom &g);
 Slot slot_at(const fizi_geom &g, uint8_t *base);

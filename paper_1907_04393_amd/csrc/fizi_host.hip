@@ -134,7 +134,7 @@ void model_at(Model &m, const fizi_geom &g, const fizi_params &p, uint8_t *base)
 size_t slot_bytes(const fizi_geom &g)
 {
     const size_t px = (size_t)g.width * g.height, words = (size_t)g.height * (g.width / 64);
-    return 2 * align256(words * 8) + 2 * align256(px * 4) + align256((px / 2) * 8);
+    return 2 * align256(words * 8) + 2 * align256(px * 4) + align256((px / 2) * 8) + align256((px / 8) * 8);
 }
 
 Slot slot_at(const fizi_geom &g, uint8_t *base)
@@ -152,6 +152,11 @@ Slot slot_at(const fizi_geom &g, uint8_t *base)
     o += align256(px * 4);
     s.runs = reinterpret_cast<uint2 *>(base + o);
     s.run_cap = (uint32_t)(px / 2);      // the most runs a mask can have
+    o += align256((px / 2) * 8);
+    // joins across band and segment borders; beyond this many, runs are
+    // flagged for the component stage instead
+    s.links = reinterpret_cast<uint2 *>(base + o);
+    s.link_cap = (uint32_t)(px / 8);
     return s;
 }
 
@@ -185,6 +190,8 @@ void set_scratch(Job &J, const Slot &s)
     J.area = s.area;
     J.runs = s.runs;
     J.run_cap = s.run_cap;
+    J.links = s.links;
+    J.link_cap = s.link_cap;
 }
 
 void set_prefixes(Table &T, int njobs, const Tuning &t)

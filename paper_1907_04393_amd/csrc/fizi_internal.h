@@ -55,11 +55,12 @@ struct Job {
     uint64_t *hand;            // H*Wd words or null
     uint32_t *parent;          // W*H: union-find parent, valid at run starts
     uint32_t *area;            // W*H: component area, valid at roots
-    uint2 *runs;               // run_cap runs (start pixel, length)
+    uint2 *runs;               // run_cap runs (first pixel, last pixel | link flag)
+    uint2 *links;              // link_cap pairs of run starts to join
     fizi_pointer *out;         // one pointer
     uint64_t frame_index;
     int32_t W, H, Wd, rs;
-    uint32_t run_cap;
+    uint32_t run_cap, link_cap;
     int32_t band;              // morphology band height (rows)
     int32_t delta, S1, open_it, close_it, min_area, fill_pm, glo, ghi;
     HueTest hue;
@@ -67,7 +68,7 @@ struct Job {
     // gain sums over usable sampled pixels, sampled row r adding to slot
     // r % kGainSlots (fewer same-address atomics)
     unsigned long long num[kGainSlots], den[kGainSlots];
-    uint32_t nruns, flags;
+    uint32_t nruns, flags, nlinks, nflag;
 };
 
 struct TableHeader {

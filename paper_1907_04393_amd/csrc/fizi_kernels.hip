@@ -664,6 +664,104 @@ __device__ __forceinline__ uint32_t run_at(int t, uint32_t ex, uint64_t st, uint
     return ex + (uint32_t)__popcll(st & (~0ull >> (63 - t))) - 1u;
 }
 
+// Inclusive max over lanes 0..l of values >= -1 (DPP as in wave_incl_scan;
+// lanes a move does not write keep -1).
+__device__ __forceinline__ int wave_incl_max(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));
+    return v;
+}
+
+// One final mask row as the lanes hold it: per word (lane + 64 c) the bits,
+// the edge bits of the neighbouring words, the run starts, the number of runs
+// starting before the word and the x of the last run start before the word.
+template <int NC>
+struct RowBits {
+    uint64_t w[NC], st[NC];
+    uint32_t lc[NC], rc[NC], ex[NC];
+    int last[NC];
+};
+
+// Fills r from the row x; en receives the run ends. Returns the row's runs.
+template <int NC>
+__device__ __forceinline__ uint32_t row_bits(RowBits<NC> &r, const uint64_t *x, int Wd, uint64_t *en)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    row_carries<NC>(x, Wd, 0u, r.lc, r.rc);
+    uint32_t total = 0;
+    int before = -1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        r.w[c] = x[c];
+        r.st[c] = x[c] & ~((x[c] << 1) | r.lc[c]);
+        en[c] = x[c] & ~((x[c] >> 1) | ((uint64_t)r.rc[c] << 63));
+        const uint32_t n = (uint32_t)__popcll(r.st[c]);
+        const uint32_t inc = wave_incl_scan(n);
+        r.ex[c] = total + inc - n;
+        total += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+        const int hi = r.st[c] ? 64 * (lane + kWave * c) + 63 - __builtin_clzll(r.st[c]) : -1;
+        const int im = wave_incl_max(hi);
+        r.last[c] = max(before, __builtin_amdgcn_update_dpp(-1, im, 0x138, 0xF, 0xF, false));
+        before = max(before, __builtin_amdgcn_readlane(im, kWave - 1));
+    }
+    return total;
+}
+
+// x of the first pixel of the run that contains bit t (set, t in [-1, 64])
+// around word c of the row.
+template <int NC>
+__device__ __forceinline__ int start_at(const RowBits<NC> &r, int c, int t)
+{
+    const int wb = 64 * ((int)(threadIdx.x & (kWave - 1)) + kWave * c);
+    if (t < 0)
+        return r.last[c];
+    uint64_t m;
+    if (t > 63) {
+        if (r.rc[c] & ~(uint32_t)(r.w[c] >> 63) & 1u)
+            return wb + 64;
+        m = r.st[c];
+    } else {
+        m = r.st[c] & (~0ull >> (63 - t));
+    }
+    return m ? wb + 63 - __builtin_clzll(m) : r.last[c];
+}
+
+// Every touching pair of runs of two consecutive rows U (above) and D
+// (below), from the lanes' words: each run start looks at the one to three
+// pixels of the other row within one column. f(c, from_d, b, t): the run
+// starting at bit b of word c of D (from_d) or U touches the run of the other
+// row that contains bit t.
+template <int NC, typename F>
+__device__ __forceinline__ void touching_runs(const RowBits<NC> &U, const RowBits<NC> &D, F f)
+{
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const RowBits<NC> &A = side == 0 ? D : U;   // starts
+            const RowBits<NC> &B = side == 0 ? U : D;   // the other row
+            uint64_t m = A.st[c];
+            while (m) {
+                const int b = __builtin_ctzll(m);
+                m &= m - 1;
+                if (bit_at(b, B.w[c], B.lc[c], B.rc[c])) {
+                    f(c, side == 0, b, b);
+                } else {
+                    if (bit_at(b - 1, B.w[c], B.lc[c], B.rc[c]))
+                        f(c, side == 0, b, b - 1);
+                    if (bit_at(b + 1, B.w[c], B.lc[c], B.rc[c]))
+                        f(c, side == 0, b, b + 1);
+                }
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ bool stage_erodes(int k, int oi, int ci) { return (k < oi) || (k >= 2 * oi + ci); }
 
 // Reserves n entries of the frame's run list (one atomic for the wave).
@@ -730,7 +828,9 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
     const int oi = J->open_it, ci = J->close_it;
     const int K = 2 * (oi + ci);
     const int y0 = band * R, y1 = min(y0 + R, H);
-    const int ya = max(0, y0 - K), yb = min(H, y1 + K);
+    // one more halo row above: row y0 - 1 is computed exactly, to join the
+    // band's first row to it without reading the band above
+    const int ya = max(0, y0 - K - 1), yb = min(H, y1 + K);
     const GLOBAL uint64_t *raw = G(J->raw);
     GLOBAL uint64_t *fz = G(J->fizi);
     GLOBAL uint32_t *parent = G(J->parent);
@@ -750,16 +850,17 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
         for (int q = 0; q < NC; ++q)
             p2[k][q] = p1[k][q] = stage_erodes(k, oi, ci) ? ~0ull : 0ull;
     uint32_t nseg = 0, prev_first = 0;
-    bool prev_in_seg = false;   // the previous row has runs in the open segment
-    bool link_next = false;     // the next row joins the row above in the component stage
-    // the previous final row: words, edge carries, run starts, runs before each word
-    uint64_t pw[NC], pst[NC];
-    uint32_t plc[NC], prc[NC], pex[NC];
+    bool prev_valid = false;    // P holds the previous row and it has runs
+    bool prev_in_seg = false;   // ... in the open segment
+    RowBits<NC> P;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        pw[c] = pst[c] = 0ull;
-        plc[c] = prc[c] = pex[c] = 0u;
+        P.w[c] = P.st[c] = 0ull;
+        P.lc[c] = P.rc[c] = P.ex[c] = 0u;
+        P.last[c] = -1;
     }
+    GLOBAL uint32_t *linkw = G(reinterpret_cast<uint32_t *>(J->links));
+    const uint32_t link_cap = J->link_cap;
     const int nsteps = (y1 - ya) + K;
     // one input row through the stages, then the band's final row it yields
     auto step = [&](int s, int q, const uint64_t (&ch)[kRawChunk][NC]) __attribute__((always_inline)) {
@@ -797,68 +898,99 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
             }
         }
         const int jrow = ya + s - K;
-        if (jrow < y0 || jrow >= y1)
+        if (jrow < 0 || jrow < y0 - 1 || jrow >= y1)
             return;
-        // a final I_FIZI row
-        GLOBAL uint64_t *frow = fz + (size_t)jrow * Wd;
         uint64_t orw = 0ull;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            if (valid_w[c])
-                frow[lane + kWave * c] = x[c];
-            else
+            if (!valid_w[c])
                 x[c] = 0ull;
             orw |= x[c];
         }
-        if (__ballot(orw != 0ull) == 0ull) {
+        const bool nonempty = __ballot(orw != 0ull) != 0ull;
+        if (jrow == y0 - 1) {
+            // the last row of the band above, only to join with
+            if (nonempty) {
+                uint64_t en[NC];
+                (void)row_bits<NC>(P, x, Wd, en);
+            }
+            prev_valid = nonempty;
             prev_in_seg = false;
-            link_next = false;
             return;
         }
-        uint32_t lcs[NC], rcs[NC];
-        row_carries<NC>(x, Wd, 0u, lcs, rcs);
-        uint64_t st[NC], en[NC];
-        uint32_t ex[NC];
-        uint32_t total = 0;
+        // a final I_FIZI row
+        GLOBAL uint64_t *frow = fz + (size_t)jrow * Wd;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            st[c] = x[c] & ~((x[c] << 1) | lcs[c]);
-            en[c] = x[c] & ~((x[c] >> 1) | ((uint64_t)rcs[c] << 63));
-            const uint32_t n = (uint32_t)__popcll(st[c]);
-            const uint32_t inc = wave_incl_scan(n);
-            ex[c] = total + inc - n;
-            total += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+        for (int c = 0; c < NC; ++c)
+            if (valid_w[c])
+                frow[lane + kWave * c] = x[c];
+        if (!nonempty) {
+            prev_valid = false;
+            return;
         }
-        bool up = (jrow == y0 && y0 > 0) || link_next;
-        link_next = false;
+        RowBits<NC> D;
+        uint64_t en[NC];
+        const uint32_t total = row_bits<NC>(D, x, Wd, en);
         if (nseg + total > (uint32_t)kSegRuns) {
             // the open segment is full: close it, this row opens the next
             flush_segment(J, L, nseg, runs, parent, area, cap);
-            up = up || prev_in_seg;
             nseg = 0;
             prev_in_seg = false;
         }
         const bool direct = total > (uint32_t)kSegRuns;
-        const uint32_t base = direct ? reserve_runs(J, total, cap) : 0u;
-        const uint32_t flag = up ? kLinkUp : 0u;
         const uint32_t rowpx = (uint32_t)jrow * (uint32_t)W;
+        // joins with a row above whose runs are not in the open segment (the
+        // band above, a closed segment, or a row written directly) go to the
+        // frame's link list as pairs of run starts
+        uint32_t flag = 0u;
+        if (prev_valid && (!prev_in_seg || direct)) {
+            uint32_t cnt = 0;
+            touching_runs<NC>(P, D, [&](int, bool, int, int) { ++cnt; });
+            const uint32_t inc = wave_incl_scan(cnt);
+            const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+            uint32_t base = 0;
+            if (lane == 0)
+                base = atomicAdd(&J->nlinks, n);
+            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+            uint32_t k = base + inc - cnt;
+            const uint32_t upx = rowpx - (uint32_t)W;
+            touching_runs<NC>(P, D, [&](int c, bool from_d, int b, int t) {
+                const uint32_t wb = 64u * (uint32_t)(lane + kWave * c);
+                const uint32_t a = from_d ? rowpx + wb + (uint32_t)b : upx + wb + (uint32_t)b;
+                const uint32_t o = from_d ? upx + (uint32_t)start_at<NC>(P, c, t)
+                                          : rowpx + (uint32_t)start_at<NC>(D, c, t);
+                if (k < link_cap) {
+                    linkw[2 * (size_t)k] = a;
+                    linkw[2 * (size_t)k + 1] = o;
+                }
+                ++k;
+            });
+            if (base + n > link_cap) {
+                // the list is full: the component stage joins this row to
+                // the row above by reading I_FIZI
+                flag = kLinkUp;
+                if (lane == 0)
+                    atomicAdd(&J->nflag, 1u);
+            }
+        }
+        const uint32_t rbase = direct ? reserve_runs(J, total, cap) : 0u;
         GLOBAL uint32_t *runw = reinterpret_cast<GLOBAL uint32_t *>(runs);
         // record the row's runs: the lane holding a run's first pixel writes
         // its start, the lane holding its last pixel its end
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const uint32_t wpx = rowpx + 64u * (uint32_t)(lane + kWave * c);
-            uint64_t m = st[c];
+            uint64_t m = D.st[c];
             while (m) {
                 const int b = __builtin_ctzll(m);
-                const uint32_t k = ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
+                const uint32_t k = D.ex[c] + (uint32_t)__popcll(D.st[c] & ((1ull << b) - 1ull));
                 m &= m - 1;
                 const uint32_t start = wpx + (uint32_t)b;
                 if (!direct) {
                     L.start[nseg + k] = start;
                     L.par[nseg + k] = nseg + k;
-                } else if (base + k < cap) {
-                    runw[2 * (size_t)(base + k)] = start;
+                } else if (rbase + k < cap) {
+                    runw[2 * (size_t)(rbase + k)] = start;
                     st_wg(parent + start, start);
                     area[start] = 0u;
                 }
@@ -866,70 +998,37 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
             m = en[c];
             while (m) {
                 const int e = __builtin_ctzll(m);
-                const uint32_t k = ex[c] + (uint32_t)__popcll(st[c] & (~0ull >> (63 - e))) - 1u;
+                const uint32_t k = D.ex[c] + (uint32_t)__popcll(D.st[c] & (~0ull >> (63 - e))) - 1u;
                 m &= m - 1;
                 const uint32_t end = (wpx + (uint32_t)e) | flag;
                 if (!direct)
                     L.end[nseg + k] = end;
-                else if (base + k < cap)
-                    runw[2 * (size_t)(base + k) + 1] = end;
+                else if (rbase + k < cap)
+                    runw[2 * (size_t)(rbase + k) + 1] = end;
             }
         }
         wave_sync();
-        if (direct) {
-            link_next = true;
-            return;
-        }
-        // join with the touching runs of the row above (same segment). Two
-        // runs of consecutive rows touch under 8-connectivity exactly when
-        // one's first pixel has a pixel of the other within one column, so
-        // each run start looks at the three pixels above (or below) it.
-        if (prev_in_seg) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                uint64_t m = st[c];
-                while (m) {
-                    const int b = __builtin_ctzll(m);
-                    const uint32_t k = nseg + ex[c] + (uint32_t)__popcll(st[c] & ((1ull << b) - 1ull));
-                    m &= m - 1;
-                    if (bit_at(b, pw[c], plc[c], prc[c])) {
-                        unite_lds(L.par, k, prev_first + run_at(b, pex[c], pst[c], pw[c], prc[c]));
-                    } else {
-                        if (bit_at(b - 1, pw[c], plc[c], prc[c]))
-                            unite_lds(L.par, k, prev_first + run_at(b - 1, pex[c], pst[c], pw[c], prc[c]));
-                        if (bit_at(b + 1, pw[c], plc[c], prc[c]))
-                            unite_lds(L.par, k, prev_first + run_at(b + 1, pex[c], pst[c], pw[c], prc[c]));
-                    }
-                }
-                m = pst[c];
-                while (m) {
-                    const int b = __builtin_ctzll(m);
-                    const uint32_t k = prev_first + pex[c] + (uint32_t)__popcll(pst[c] & ((1ull << b) - 1ull));
-                    m &= m - 1;
-                    if (bit_at(b, x[c], lcs[c], rcs[c])) {
-                        unite_lds(L.par, k, nseg + run_at(b, ex[c], st[c], x[c], rcs[c]));
-                    } else {
-                        if (bit_at(b - 1, x[c], lcs[c], rcs[c]))
-                            unite_lds(L.par, k, nseg + run_at(b - 1, ex[c], st[c], x[c], rcs[c]));
-                        if (bit_at(b + 1, x[c], lcs[c], rcs[c]))
-                            unite_lds(L.par, k, nseg + run_at(b + 1, ex[c], st[c], x[c], rcs[c]));
-                    }
-                }
-            }
+        // joins with the row above in the open segment, in the LDS union-find
+        if (prev_valid && prev_in_seg && !direct) {
+            touching_runs<NC>(P, D, [&](int c, bool from_d, int b, int t) {
+                const uint64_t below = (1ull << b) - 1ull;
+                if (from_d)
+                    unite_lds(L.par, nseg + D.ex[c] + (uint32_t)__popcll(D.st[c] & below),
+                              prev_first + run_at(t, P.ex[c], P.st[c], P.w[c], P.rc[c]));
+                else
+                    unite_lds(L.par, prev_first + P.ex[c] + (uint32_t)__popcll(P.st[c] & below),
+                              nseg + run_at(t, D.ex[c], D.st[c], D.w[c], D.rc[c]));
+            });
             wave_sync();
         }
         // this row becomes the row above
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            pw[c] = x[c];
-            pst[c] = st[c];
-            plc[c] = lcs[c];
-            prc[c] = rcs[c];
-            pex[c] = ex[c];
+        P = D;
+        prev_valid = true;
+        prev_in_seg = !direct;
+        if (!direct) {
+            prev_first = nseg;
+            nseg += total;
         }
-        prev_first = nseg;
-        nseg += total;
-        prev_in_seg = true;
     };
     // input chunks alternate between two register buffers: each is loaded a
     // chunk ahead of its use, straight into the registers that use it
@@ -1004,18 +1103,26 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
     if (hand)
         for (int i = threadIdx.x; i < H * Wd; i += blockDim.x)
             hand[i] = 0ull;
-    // A: flagged runs (first rows of bands and segments) join the row above
-    for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
-        const uint64_t rv = runs[i];
-        if (!((uint32_t)(rv >> 32) & kLinkUp))
-            continue;
-        const uint2 rn = unpack_run(rv);
-        const int y = (int)(rn.x / (uint32_t)W);
-        if (y == 0)
-            continue;
-        const int xs = (int)(rn.x - (uint32_t)y * W), xe = xs + (int)rn.y - 1;
-        link_up(parent, fz + (size_t)(y - 1) * Wd, Wd, W, y, xs, xe, rn.x);
+    // A: joins across band and segment borders (pairs of run starts), and
+    // runs flagged when the pair list was full, joined by reading I_FIZI
+    const uint32_t nl = min(ld_dev(&J->nlinks), J->link_cap);
+    const GLOBAL uint64_t *links = G(reinterpret_cast<const uint64_t *>(J->links));
+    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
+        const uint64_t l = links[i];
+        unite(parent, (uint32_t)l, (uint32_t)(l >> 32));
     }
+    if (ld_dev(&J->nflag))
+        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+            const uint64_t rv = runs[i];
+            if (!((uint32_t)(rv >> 32) & kLinkUp))
+                continue;
+            const uint2 rn = unpack_run(rv);
+            const int y = (int)(rn.x / (uint32_t)W);
+            if (y == 0)
+                continue;
+            const int xs = (int)(rn.x - (uint32_t)y * W), xe = xs + (int)rn.y - 1;
+            link_up(parent, fz + (size_t)(y - 1) * Wd, Wd, W, y, xs, xe, rn.x);
+        }
     __syncthreads();
     // B: roots and areas
     uint32_t ncomp = 0;
