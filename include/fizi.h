@@ -196,7 +196,9 @@ typedef struct fizi_batch fizi_batch;
 enum {
     FIZI_BATCH_DIRECT = 0,            /* four kernels per step, launched directly */
     FIZI_BATCH_GRAPH = 1,             /* the same, replayed from a hipGraph */
-    FIZI_BATCH_PERSISTENT = 2,        /* one persistent fused kernel per step */
+    FIZI_BATCH_PERSISTENT = 2,        /* one persistent kernel per step, fed by an ordered
+                                         work queue: gain tiles, row bands (classify, then
+                                         morphology of the band above) and components overlap */
     FIZI_BATCH_PERSISTENT_GRAPH = 3   /* the persistent kernel from a hipGraph */
 };
 
@@ -224,7 +226,7 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
 int fizi_batch_set_mode(fizi_batch *b, int32_t mode);
 
 /* Waits for all steps and returns (and clears) the error word: non-zero when
- * a persistent step gave up waiting at a grid barrier (its outputs are then
+ * a persistent step gave up one of its bounded waits (its outputs are then
  * not valid). */
 int fizi_batch_status(fizi_batch *b, uint32_t *h_flags);
 
@@ -238,10 +240,11 @@ int fizi_batch_stage_timing(fizi_batch *b, int32_t enable);
 int fizi_batch_stage_times(fizi_batch *b, double *h_ms, int64_t *h_launches);
 
 /* Launch shapes of a batch. cls_iters: classify tile = 1024 * cls_iters
- * pixels (1, 2, 4, 8; the persistent kernel uses 2, 4 or 8); morph_rows:
- * morphology band height (8, 16, 32, 64); grid_per_cu: resident blocks per
- * CU for the streaming kernels
- * (1..32); mode: FIZI_BATCH_*. Results do not depend on them. */
+ * pixels (1, 2, 4, 8; not used by the persistent kernel, whose classify
+ * work comes in bands of 4 * morph_rows rows); morph_rows: morphology band
+ * height (8, 16, 32, 64); grid_per_cu: resident blocks per CU for the
+ * streaming kernels (1..32); mode: FIZI_BATCH_*. Results do not depend on
+ * them. */
 typedef struct {
     int32_t cls_iters;
     int32_t morph_rows;

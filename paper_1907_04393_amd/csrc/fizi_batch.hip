@@ -15,6 +15,7 @@ struct fizi_batch {
     std::vector<Model> m;
     std::vector<Slot> slot;
     std::vector<uint64_t> frames;      // frames stepped per stream
+    std::vector<uint32_t> epoch;       // dispatches per stream slot (band flag values)
     Tuning tune{};
     int max_wd = 0, max_ops = 0;
     uint8_t *d = nullptr;
@@ -162,6 +163,7 @@ int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_para
     b->m.resize(n_streams);
     b->slot.resize(n_streams);
     b->frames.assign(n_streams, 0);
+    b->epoch.assign(n_streams, 0);
     int max_w = 0;
     for (int i = 0; i < n_streams; ++i) {
         model_at(b->m[i], geoms[i], params[i], b->d + L.model[i]);
@@ -180,6 +182,9 @@ int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_para
         if (e == hipSuccess)
             e = (hipError_t)launch_fill_u32(reinterpret_cast<uint32_t *>(b->persist), 0u,
                                              persist_state_bytes() / 4, nullptr);
+        // band flags hold no epoch yet (epochs start at 1)
+        for (int i = 0; i < n_streams && e == hipSuccess; ++i)
+            e = (hipError_t)launch_fill_u32(b->slot[i].bflag, 0u, b->slot[i].nflags, nullptr);
         if (e == hipSuccess)
             e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess)
@@ -253,6 +258,9 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
             J.fizi = h_fizi_bits[i];
         J.out = d_pointers + i;
         J.frame_index = b->frames[i]++;
+        if (++b->epoch[i] == 0)
+            b->epoch[i] = 1;
+        J.epoch = b->epoch[i];
     }
     set_prefixes(T, k, b->tune);
     const bool graphed = b->mode == FIZI_BATCH_GRAPH || b->mode == FIZI_BATCH_PERSISTENT_GRAPH;
@@ -287,11 +295,8 @@ int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t)
 {
     if (!b || !t)
         return fail(FIZI_EINVAL, "null argument");
-    const bool persistent = t->mode == FIZI_BATCH_PERSISTENT || t->mode == FIZI_BATCH_PERSISTENT_GRAPH;
     if (t->cls_iters != 1 && t->cls_iters != 2 && t->cls_iters != 4 && t->cls_iters != 8)
         return fail(FIZI_EINVAL, "cls_iters must be 1, 2, 4 or 8");
-    if (persistent && t->cls_iters == 1)
-        return fail(FIZI_EINVAL, "the persistent kernel takes cls_iters 2, 4 or 8");
     if (t->morph_rows != 8 && t->morph_rows != 16 && t->morph_rows != 32 && t->morph_rows != 64)
         return fail(FIZI_EINVAL, "morph_rows must be 8, 16, 32 or 64");
     if (t->grid_per_cu < 1 || t->grid_per_cu > 32)

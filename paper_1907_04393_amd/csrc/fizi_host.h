@@ -63,8 +63,12 @@ struct Slot {
     uint32_t *area = nullptr;
     uint2 *runs = nullptr;
     uint2 *links = nullptr;
+    uint32_t *bflag = nullptr;           // persistent step: per band epoch
     uint32_t run_cap = 0, link_cap = 0;
+    size_t nflags = 0;
 };
+// Band flags of the persistent step: one per 32 rows (its smallest band).
+inline size_t flag_words(const fizi_geom &g) { return (size_t)(g.height + 31) / 32; }
 size_t slot_bytes(const fizi_geom &g);
 Slot slot_at(const fizi_geom &g, uint8_t *base);
 

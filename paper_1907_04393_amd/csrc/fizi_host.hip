@@ -134,7 +134,8 @@ void model_at(Model &m, const fizi_geom &g, const fizi_params &p, uint8_t *base)
 size_t slot_bytes(const fizi_geom &g)
 {
     const size_t px = (size_t)g.width * g.height, words = (size_t)g.height * (g.width / 64);
-    return 2 * align256(words * 8) + 2 * align256(px * 4) + align256((px / 2) * 8) + align256((px / 8) * 8);
+    return 2 * align256(words * 8) + 2 * align256(px * 4) + align256((px / 2) * 8) + align256((px / 8) * 8) +
+           align256(flag_words(g) * 4);
 }
 
 Slot slot_at(const fizi_geom &g, uint8_t *base)
@@ -157,6 +158,9 @@ Slot slot_at(const fizi_geom &g, uint8_t *base)
     // flagged for the component stage instead
     s.links = reinterpret_cast<uint2 *>(base + o);
     s.link_cap = (uint32_t)(px / 8);
+    o += align256((px / 8) * 8);
+    s.bflag = reinterpret_cast<uint32_t *>(base + o);
+    s.nflags = flag_words(g);
     return s;
 }
 
@@ -192,6 +196,7 @@ void set_scratch(Job &J, const Slot &s)
     J.run_cap = s.run_cap;
     J.links = s.links;
     J.link_cap = s.link_cap;
+    J.bflag = s.bflag;
 }
 
 void set_prefixes(Table &T, int njobs, const Tuning &t)
@@ -207,6 +212,30 @@ void set_prefixes(Table &T, int njobs, const Tuning &t)
         T.h.cls_pre[i + 1] = T.h.cls_pre[i] + (int)((px + ctile - 1) / ctile);
         T.h.mor_pre[i + 1] = T.h.mor_pre[i] + (J.H + t.morph_rows - 1) / t.morph_rows;
     }
+    // the persistent step's queue: jobs by size, largest first; every gain
+    // tile ahead of the bands, so that a band rarely waits for its frame's
+    // gain
+    int order[kMaxJobs];
+    for (int i = 0; i < njobs; ++i)
+        order[i] = i;
+    std::stable_sort(order, order + njobs, [&](int a, int b) {
+        return (long)T.jobs[a].W * T.jobs[a].H > (long)T.jobs[b].W * T.jobs[b].H;
+    });
+    int k = 0, item = 0;
+    auto push = [&](int j, int type) {
+        const int n = type == 0 ? T.h.gain_pre[j + 1] - T.h.gain_pre[j]
+                                : (T.jobs[j].H + 4 * t.morph_rows - 1) / (4 * t.morph_rows);
+        T.h.flow_pre[k] = item;
+        T.h.flow_seg[k] = (j << 1) | type;
+        item += n;
+        ++k;
+    };
+    for (int i = 0; i < njobs; ++i)
+        push(order[i], 0);
+    for (int i = 0; i < njobs; ++i)
+        push(order[i], 1);
+    T.h.flow_nseg = k;
+    T.h.flow_pre[k] = item;
 }
 
 int TableRing::init(uint8_t *d_base)

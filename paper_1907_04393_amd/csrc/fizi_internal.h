@@ -8,7 +8,8 @@
 // which also zeroes the accumulators for that call. Every kernel walks a flat
 // list of tiles (grid-stride) and finds a tile's job by binary search in a
 // prefix array, so one launch covers frames of any mix of resolutions and a
-// launch's shape does not depend on the work it is given.
+// launch's shape does not depend on the work it is given. The persistent
+// step instead takes work items from an ordered queue (see TableHeader).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,6 +55,7 @@ struct Job {
     uint64_t *fizi;            // H*Wd words: after opening and closing
     uint64_t *hand;            // H*Wd words or null
     uint32_t *parent;          // W*H: union-find parent, valid at run starts
+    uint32_t *bflag;           // per row band of the persistent step: epoch when classified
     uint32_t *area;            // W*H: component area, valid at roots
     uint2 *runs;               // run_cap runs (first pixel, last pixel | link flag)
     uint2 *links;              // link_cap pairs of run starts to join
@@ -61,6 +63,7 @@ struct Job {
     uint64_t frame_index;
     int32_t W, H, Wd, rs;
     uint32_t run_cap, link_cap;
+    uint32_t epoch;            // this dispatch's number for its scratch slot (never 0)
     int32_t band;              // morphology band height (rows)
     int32_t delta, S1, open_it, close_it, min_area, fill_pm, glo, ghi;
     HueTest hue;
@@ -69,15 +72,26 @@ struct Job {
     // r % kGainSlots (fewer same-address atomics)
     unsigned long long num[kGainSlots], den[kGainSlots];
     uint32_t nruns, flags, nlinks, nflag;
+    uint32_t gain_done, morph_done;   // persistent step: finished gain tiles, morphology bands
+    uint32_t ginv;                    // persistent step: 0x80000000 | inverse gain, once known
+    uint32_t pad2;
 };
 
+// The persistent step's queue: segments of work items, in order
+//   gain(o0), ..., gain(o[n-1]), bands(o0), ..., bands(o[n-1])
+// over the jobs o sorted by size, largest first. A gain item is one gain
+// tile; a band item is 4 * band rows: classify them, then run the
+// morphology of the band above (and, for the last band, of this one) and,
+// when a frame's last band is done, its components. An item only ever waits
+// for items earlier in the queue.
 struct TableHeader {
     int32_t njobs;
-    int32_t pad0;
+    int32_t flow_nseg;                    // 2 * njobs
     int32_t gain_pre[kMaxJobs + 1];   // gain tiles (kGainRows sampled rows)
     int32_t cls_pre[kMaxJobs + 1];    // classify tiles
     int32_t mor_pre[kMaxJobs + 1];    // morphology bands
-    int32_t pad1;
+    int32_t flow_pre[2 * kMaxJobs + 1];   // first item of each queue segment
+    int32_t flow_seg[2 * kMaxJobs];       // (job << 1) | (0: gain, 1: bands)
 };
 
 struct Table {
@@ -96,12 +110,11 @@ struct Tuning {
 
 inline int cls_tile_px(const Tuning &t) { return 1024 * t.cls_iters; }
 
-// Counters of the persistent fused step's grid barriers (device memory,
-// zero between launches).
+// Counters of the persistent step (device memory, zero between launches).
 struct PersistState {
-    unsigned int arrived;    // barrier arrivals in the current launch
+    unsigned int next;       // next queue item of the current launch
     unsigned int finished;   // blocks done with the current launch
-    unsigned int error;      // a barrier wait gave up (sticky until read)
+    unsigned int error;      // a bounded wait gave up (sticky until read)
     unsigned int pad[61];
 };
 inline size_t persist_state_bytes() { return sizeof(PersistState); }

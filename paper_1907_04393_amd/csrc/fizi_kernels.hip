@@ -58,6 +58,40 @@ __device__ __forceinline__ T ld_dev(const T *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Persistent step: data that a workgroup hands to another one in the same
+// launch is stored with device scope (written through this XCD's L2), each
+// wave waits for its stores to complete before the workgroup bumps the
+// counter or flag the consumer polls, and the consumer takes a device-scope
+// acquire fence after seeing it, so that its loads miss any stale copy.
+template <typename T>
+__device__ __forceinline__ void st_dev(GLOBAL T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A store of the morphology/classify stages: device scope in the persistent
+// step (FLOW), plain otherwise.
+template <bool FLOW, typename T>
+__device__ __forceinline__ void put(GLOBAL T *p, T v)
+{
+    if constexpr (FLOW)
+        st_dev(p, v);
+    else
+        *p = v;
+}
+
+// Union-find parent stores of the morphology stage.
+template <bool FLOW>
+__device__ __forceinline__ void put_parent(GLOBAL uint32_t *p, uint32_t v)
+{
+    if constexpr (FLOW)
+        st_dev(p, v);
+    else
+        st_wg(p, v);
+}
+
+__device__ __forceinline__ void wait_own_memory() { __builtin_amdgcn_s_waitcnt(0); }
+
 __device__ __forceinline__ int find_job(const int32_t *pre, int nj, int t)
 {
     int lo = 0, hi = nj - 1;          // largest j with pre[j] <= t
@@ -324,78 +358,171 @@ __global__ __launch_bounds__(256) void k_minmax(Table *__restrict__ T, int nj,
 // 12 of bgmax); a wave covers 256 pixels = 4 mask words. The hue and gray
 // tests only run for pixels already outside the background box, so waves of
 // pure background skip them.
-template <int ITERS>
-__device__ __forceinline__ void classify_tile(Table *__restrict__ T, int j, int tile, bool same_launch)
+// What classify needs of a frame's job, read once into registers (the raw
+// mask stores could otherwise alias the job table and force reloads).
+struct ClsJob {
+    const GLOBAL uint32_t *fr, *mn, *mx;
+    GLOBAL uint64_t *raw;
+    int delta, S1;
+    HueTest h;
+};
+
+__device__ __forceinline__ ClsJob cls_job(const Job *J)
 {
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    ClsJob c;
+    c.fr = G(reinterpret_cast<const uint32_t *>(J->frame));
+    c.mn = G(reinterpret_cast<const uint32_t *>(J->bgmin));
+    c.mx = G(reinterpret_cast<const uint32_t *>(J->bgmax));
+    c.raw = G(J->raw);
+    c.delta = J->delta;
+    c.S1 = J->S1;
+    c.h = J->hue;
+    return c;
+}
+
+// The inputs of one lane's 4 pixels: frame, background min and max (3 dwords each).
+struct Px4 {
+    uint32_t f[3], l[3], u[3];
+};
+
+__device__ __forceinline__ void load_px4(const ClsJob &c, uint32_t p, uint32_t pend, Px4 &x)
+{
+    if (p < pend) {
+        const uint32_t q = 3u * (p >> 2);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            x.f[k] = c.fr[q + k];
+            x.l[k] = c.mn[q + k];
+            x.u[k] = c.mx[q + k];
+        }
+    }
+}
+
+// I_R1, I_R2 and I_R3 of one 1024-pixel unit of a frame (256 per wave, 4 per
+// lane) whose pixels from pend on are not classified; base is the wave's
+// first pixel (a multiple of 64), raw words at or past pend / 64 are not
+// written; x holds the lane's inputs (loaded by load_px4).
+template <bool FLOW>
+__device__ __forceinline__ void classify_px4(const ClsJob &c, uint32_t base, uint32_t pend, uint32_t inv,
+                                             const Px4 &x)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t p = base + 4u * lane;
+    uint32_t bits = 0;
+    if (p < pend) {
+        int cv[12];
+        uint32_t out = 0;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const int v = (int)corr(byte_of(x.f[0], x.f[1], x.f[2], i), inv);
+            const int lo = (int)byte_of(x.l[0], x.l[1], x.l[2], i) - c.delta;
+            const int hi = (int)byte_of(x.u[0], x.u[1], x.u[2], i) + c.delta;
+            cv[i] = v;
+            out |= (uint32_t)((v < lo) | (v > hi)) << (i / 3);
+        }
+        if (out) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (out & (1u << k)) {
+                    const int r = cv[3 * k], g = cv[3 * k + 1], b = cv[3 * k + 2];
+                    const int ch = max(max(r, g), b) - min(min(r, g), b);
+                    if (ch >= c.S1 && hue_in(r, g, b, c.h))
+                        bits |= 1u << k;
+                }
+            }
+        }
+    }
+    const uint64_t b0 = __ballot(bits & 1u), b1 = __ballot(bits & 2u),
+                   b2 = __ballot(bits & 4u), b3 = __ballot(bits & 8u);
+    if (lane < 4) {
+        const uint32_t word = (base >> 6) + lane;
+        const int sh = 16 * lane;
+        if (word < (pend >> 6))
+            put<FLOW>(c.raw + word, spread4(b0 >> sh) | (spread4(b1 >> sh) << 1) | (spread4(b2 >> sh) << 2) |
+                                        (spread4(b3 >> sh) << 3));
+    }
+}
+
+// The wave's units of pixels [p0, p1) of a frame (p0 a multiple of 64):
+// 1024 pixels apart, each unit's inputs loaded one unit ahead into
+// alternating registers.
+template <bool FLOW>
+__device__ __forceinline__ void classify_span(const ClsJob &c, uint32_t p0, uint32_t p1, uint32_t inv)
+{
+    const uint32_t lanepx = 4u * (threadIdx.x & (kWave - 1));
+    uint32_t base = p0 + (uint32_t)(threadIdx.x / kWave) * 256u;
+    Px4 a, b;
+    load_px4(c, base + lanepx, p1, a);
+    while (base < p1) {
+        load_px4(c, base + 1024u + lanepx, p1, b);
+        classify_px4<FLOW>(c, base, p1, inv, a);
+        base += 1024u;
+        if (base >= p1)
+            break;
+        load_px4(c, base + 1024u + lanepx, p1, a);
+        classify_px4<FLOW>(c, base, p1, inv, b);
+        base += 1024u;
+    }
+}
+
+// Classify tile `tile` of frame j: ITERS consecutive 1024-pixel units.
+template <int ITERS>
+__device__ __forceinline__ void classify_tile(Table *__restrict__ T, int j, int tile, uint32_t inv)
+{
+    const int wave = threadIdx.x / kWave;
     const Job *J = &T->jobs[j];
     const uint32_t npx = (uint32_t)J->W * (uint32_t)J->H;
-    const uint32_t inv = job_gain(J, same_launch);
-    const int delta = J->delta, S1 = J->S1;
-    const HueTest h = J->hue;
-    const GLOBAL uint32_t *fr = G(reinterpret_cast<const uint32_t *>(J->frame));
-    const GLOBAL uint32_t *mnp = G(reinterpret_cast<const uint32_t *>(J->bgmin));
-    const GLOBAL uint32_t *mxp = G(reinterpret_cast<const uint32_t *>(J->bgmax));
-    GLOBAL uint64_t *raw = G(J->raw);
+    const ClsJob c = cls_job(J);
+    const uint32_t lanepx = 4u * (threadIdx.x & (kWave - 1));
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
         const uint32_t base = ((uint32_t)tile * ITERS + it) * 1024u + (uint32_t)wave * 256u;
         if (base >= npx)
             break;
-        const uint32_t p = base + 4u * lane;
-        uint32_t bits = 0;
-        if (p < npx) {
-            const uint32_t q = 3u * (p >> 2);
-            const uint32_t f0 = fr[q], f1 = fr[q + 1], f2 = fr[q + 2];
-            const uint32_t l0 = mnp[q], l1 = mnp[q + 1], l2 = mnp[q + 2];
-            const uint32_t u0 = mxp[q], u1 = mxp[q + 1], u2 = mxp[q + 2];
-            int cv[12];
-            uint32_t out = 0;
-#pragma unroll
-            for (int i = 0; i < 12; ++i) {
-                const int v = (int)corr(byte_of(f0, f1, f2, i), inv);
-                const int lo = (int)byte_of(l0, l1, l2, i) - delta;
-                const int hi = (int)byte_of(u0, u1, u2, i) + delta;
-                cv[i] = v;
-                out |= (uint32_t)((v < lo) | (v > hi)) << (i / 3);
-            }
-            if (out) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (out & (1u << k)) {
-                        const int r = cv[3 * k], g = cv[3 * k + 1], b = cv[3 * k + 2];
-                        const int c = max(max(r, g), b) - min(min(r, g), b);
-                        if (c >= S1 && hue_in(r, g, b, h))
-                            bits |= 1u << k;
-                    }
-                }
-            }
-        }
-        const uint64_t b0 = __ballot(bits & 1u), b1 = __ballot(bits & 2u),
-                       b2 = __ballot(bits & 4u), b3 = __ballot(bits & 8u);
-        if (lane < 4) {
-            const uint32_t word = (base >> 6) + lane;
-            const int sh = 16 * lane;
-            if (word < (npx >> 6))
-                raw[word] = spread4(b0 >> sh) | (spread4(b1 >> sh) << 1) |
-                            (spread4(b2 >> sh) << 2) | (spread4(b3 >> sh) << 3);
-        }
+        Px4 x;
+        load_px4(c, base + lanepx, npx, x);
+        classify_px4<false>(c, base, npx, inv, x);
+    }
+}
+
+// Per block, once: the tile prefix and every frame's inverse gain in LDS, so
+// a tile costs neither a search nor a division.
+__device__ __forceinline__ void stage_jobs(Table *__restrict__ T, int nj, int32_t *s_pre, uint32_t *s_inv,
+                                           bool same_launch)
+{
+    for (int i = threadIdx.x; i <= nj; i += blockDim.x)
+        s_pre[i] = T->h.cls_pre[i];
+    for (int i = threadIdx.x; i < nj; i += blockDim.x)
+        s_inv[i] = job_gain(&T->jobs[i], same_launch);
+    __syncthreads();
+}
+
+// Tiles blockIdx.x, blockIdx.x + gridDim.x, ...: the frame index only grows,
+// so it is advanced, not searched.
+template <int ITERS>
+__device__ __forceinline__ void classify_tiles(Table *__restrict__ T, int nj, const int32_t *s_pre,
+                                               const uint32_t *s_inv)
+{
+    const int total = s_pre[nj];
+    int j = 0;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        while (s_pre[j + 1] <= t)
+            ++j;
+        classify_tile<ITERS>(T, j, t - s_pre[j], s_inv[j]);
     }
 }
 
 template <int ITERS>
 __global__ __launch_bounds__(256) void k_classify(Table *__restrict__ T)
 {
+    __shared__ int32_t s_pre[kMaxJobs + 1];
+    __shared__ uint32_t s_inv[kMaxJobs];
     const int nj = T->h.njobs;
-    const int total = T->h.cls_pre[nj];
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const int j = find_job(T->h.cls_pre, nj, t);
-        classify_tile<ITERS>(T, j, t - T->h.cls_pre[j], false);
-    }
+    stage_jobs(T, nj, s_pre, s_inv, false);
+    classify_tiles<ITERS>(T, nj, s_pre, s_inv);
 }
 
 // ---------------------------------------------------------------------------
-// A run is packed as (length << 32) | start pixel.
 // A run list entry: first pixel (low word), last pixel (bits 32..62) and the
 // flag kLinkUp (bit 63): the run must still be joined to the row above.
 constexpr uint32_t kLinkUp = 0x80000000u;
@@ -778,6 +905,7 @@ __device__ __forceinline__ uint32_t reserve_runs(Job *J, uint32_t n, uint32_t ca
 }
 
 // Closes a segment: its n runs join the run list, each pointing at its root.
+template <bool FLOW>
 __device__ __forceinline__ void flush_segment(Job *J, WaveLds &L, uint32_t n, GLOBAL uint64_t *runs,
                                               GLOBAL uint32_t *parent, GLOBAL uint32_t *area, uint32_t cap)
 {
@@ -789,9 +917,9 @@ __device__ __forceinline__ void flush_segment(Job *J, WaveLds &L, uint32_t n, GL
         const uint32_t st = L.start[k];
         const uint32_t r = find_lds(L.par, k);
         if (base + k < cap) {
-            runs[base + k] = ((uint64_t)L.end[k] << 32) | st;
-            st_wg(parent + st, L.start[r]);
-            area[st] = 0u;
+            put<FLOW>(runs + base + k, ((uint64_t)L.end[k] << 32) | st);
+            put_parent<FLOW>(parent + st, L.start[r]);
+            put<FLOW>(area + st, 0u);
         }
     }
     wave_sync();
@@ -816,14 +944,12 @@ __device__ __forceinline__ void load_rows(uint64_t (&dst)[kRawChunk][NC], const 
     }
 }
 
-// KMAX: most opening/closing stages a job may have; NC: words per lane.
-template <int KMAX, int NC>
-__device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t, WaveLds &L)
+// KMAX: most opening/closing stages a job may have; NC: words per lane; FLOW:
+// inside the persistent step (stores other workgroups read in the launch).
+template <int KMAX, int NC, bool FLOW>
+__device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int j = find_job(T->h.mor_pre, nj, t);
-    Job *J = &T->jobs[j];
-    const int band = t - T->h.mor_pre[j];
     const int W = J->W, H = J->H, Wd = J->Wd, R = J->band;
     const int oi = J->open_it, ci = J->close_it;
     const int K = 2 * (oi + ci);
@@ -923,7 +1049,7 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (valid_w[c])
-                frow[lane + kWave * c] = x[c];
+                put<FLOW>(frow + lane + kWave * c, x[c]);
         if (!nonempty) {
             prev_valid = false;
             return;
@@ -933,7 +1059,7 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
         const uint32_t total = row_bits<NC>(D, x, Wd, en);
         if (nseg + total > (uint32_t)kSegRuns) {
             // the open segment is full: close it, this row opens the next
-            flush_segment(J, L, nseg, runs, parent, area, cap);
+            flush_segment<FLOW>(J, L, nseg, runs, parent, area, cap);
             nseg = 0;
             prev_in_seg = false;
         }
@@ -960,8 +1086,8 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
                 const uint32_t o = from_d ? upx + (uint32_t)start_at<NC>(P, c, t)
                                           : rowpx + (uint32_t)start_at<NC>(D, c, t);
                 if (k < link_cap) {
-                    linkw[2 * (size_t)k] = a;
-                    linkw[2 * (size_t)k + 1] = o;
+                    put<FLOW>(linkw + 2 * (size_t)k, a);
+                    put<FLOW>(linkw + 2 * (size_t)k + 1, o);
                 }
                 ++k;
             });
@@ -990,9 +1116,9 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
                     L.start[nseg + k] = start;
                     L.par[nseg + k] = nseg + k;
                 } else if (rbase + k < cap) {
-                    runw[2 * (size_t)(rbase + k)] = start;
-                    st_wg(parent + start, start);
-                    area[start] = 0u;
+                    put<FLOW>(runw + 2 * (size_t)(rbase + k), start);
+                    put_parent<FLOW>(parent + start, start);
+                    put<FLOW>(area + start, 0u);
                 }
             }
             m = en[c];
@@ -1004,7 +1130,7 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
                 if (!direct)
                     L.end[nseg + k] = end;
                 else if (rbase + k < cap)
-                    runw[2 * (size_t)(rbase + k) + 1] = end;
+                    put<FLOW>(runw + 2 * (size_t)(rbase + k) + 1, end);
             }
         }
         wave_sync();
@@ -1045,7 +1171,7 @@ __device__ __forceinline__ void morph_band(Table *__restrict__ T, int nj, int t,
         for (int q = 0; q < kRawChunk && s0 + kRawChunk + q < nsteps; ++q)
             step(s0 + kRawChunk + q, q, cb);
     }
-    flush_segment(J, L, nseg, runs, parent, area, cap);
+    flush_segment<FLOW>(J, L, nseg, runs, parent, area, cap);
 }
 
 template <int KMAX, int NC>
@@ -1056,7 +1182,10 @@ __global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T)
     const int nj = T->h.njobs;
     const int total = T->h.mor_pre[nj];
     for (int t = blockIdx.x * (256 / kWave) + wave; t < total; t += gridDim.x * (256 / kWave))
-        morph_band<KMAX, NC>(T, nj, t, s_wl[wave]);
+    {
+        const int j = find_job(T->h.mor_pre, nj, t);
+        morph_band<KMAX, NC, false>(&T->jobs[j], t - T->h.mor_pre[j], s_wl[wave]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1219,68 +1348,134 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(Table *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Persistent fused step: the four stages of one frame step in one launch,
-// separated by grid-wide barriers. The grid never exceeds the blocks that can
-// be resident at once. Every wait is bounded: a block that waits too long
-// sets the error word and skips the remaining stages, so every block reaches
-// the end of the kernel; the last block to finish resets the counters for the
-// next launch.
-constexpr unsigned kSpinLimit = 1u << 20;
+// Persistent step: one launch per frame step whose workgroups take work items
+// from the ordered queue of the job table (TableHeader) with one atomic
+// counter. A gain item is one gain tile. A band item classifies 4 * band
+// rows of a frame (once the frame's gain is complete), publishes them, then
+// runs the morphology of the band above - its four waves take one sub-band
+// each - once the bands it reads are published, and of its own band when it
+// is the frame's last; the workgroup that completes a frame's last
+// morphology band then resolves its components. Latency-bound morphology and
+// components thus run while other workgroups stream later bands. Items only
+// wait for items earlier in the queue, which are held by running workgroups
+// that never wait for later ones, so every wait ends. Each wait is bounded
+// (50 ms of the 100 MHz clock); one that gives up sets the error word and
+// goes on, so that every workgroup reaches the end; the last one out resets
+// the queue for the next launch.
+constexpr uint64_t kWaitTicks = 5000000;
 
-__device__ __forceinline__ bool grid_sync(PersistState *ps, unsigned k)
+// Thread 0 waits until the counter reaches target, or the flag equals it.
+__device__ __forceinline__ void spin_until(const uint32_t *p, uint32_t target, bool equal, PersistState *ps,
+                                           uint64_t t0)
 {
-    __shared__ int s_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();   // release this block's writes to the other blocks
-        atomicAdd(&ps->arrived, 1u);
-        const unsigned target = k * gridDim.x;
-        unsigned spins = 0;
-        int ok = 1;
-        while (__hip_atomic_load(&ps->arrived, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++spins > kSpinLimit) {
-                atomicOr(&ps->error, 1u);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
+    for (;;) {
+        const uint32_t v = ld_dev(p);
+        if (equal ? v == target : v >= target)
+            return;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
+            atomicOr(&ps->error, 1u);
+            return;
         }
-        if (__hip_atomic_load(&ps->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            ok = 0;
-        __threadfence();   // acquire the other blocks' writes
-        s_ok = ok;
+        __builtin_amdgcn_s_sleep(1);
     }
-    __syncthreads();
-    return s_ok != 0;
 }
 
-template <int ITERS, int KMAX, int NC>
-__global__ __launch_bounds__(256) void k_step(Table *__restrict__ T, PersistState *ps)
+// After thread 0's waits: a device-scope acquire, then the workgroup goes on.
+__device__ __forceinline__ void acquire_for_block()
 {
-    const int nj = T->h.njobs;
-    for_block_tiles(T->h.gain_pre, nj, [&](int j, int tile) { gain_tile(T, j, tile); });
-    bool ok = grid_sync(ps, 1);
-    if (ok)
-        for (int t = blockIdx.x; t < T->h.cls_pre[nj]; t += gridDim.x) {
-            const int j = find_job(T->h.cls_pre, nj, t);
-            classify_tile<ITERS>(T, j, t - T->h.cls_pre[j], true);
+    if (threadIdx.x == 0)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+}
+
+// Every wave's stores complete, then thread 0 adds v to the counter; returns
+// the counter's previous value to the whole workgroup.
+__device__ __forceinline__ uint32_t publish_add(uint32_t *p, uint32_t v, uint32_t *s_old)
+{
+    wait_own_memory();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *s_old = atomicAdd(p, v);
+    __syncthreads();
+    return *s_old;
+}
+
+template <int KMAX, int NC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX == 4 && NC == 1 ? 4 : 1))) void k_flow(Table *__restrict__ T, PersistState *ps)
+{
+    __shared__ WaveLds s_wl[256 / kWave];
+    __shared__ int s_item;
+    __shared__ uint32_t s_u;
+    const int wave = threadIdx.x / kWave;
+    const int nseg = T->h.flow_nseg;
+    const int total = T->h.flow_pre[nseg];
+    int k = 0;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = (int)atomicAdd(&ps->next, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total)
+            break;
+        while (T->h.flow_pre[k + 1] <= item)
+            ++k;
+        const int seg = T->h.flow_seg[k], j = seg >> 1, idx = item - T->h.flow_pre[k];
+        Job *J = &T->jobs[j];
+        if ((seg & 1) == 0) {
+            gain_tile(T, j, idx);
+            const uint32_t ng = (uint32_t)(T->h.gain_pre[j + 1] - T->h.gain_pre[j]);
+            if (publish_add(&J->gain_done, 1u, &s_u) + 1u == ng && threadIdx.x == 0) {
+                // the frame's last gain tile: its inverse gain, once, for every band
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                st_dev(G(&J->ginv), 0x80000000u | job_gain(J, true));
+            }
+            continue;
         }
-    ok = grid_sync(ps, 2) && ok;
-    if (ok) {
-        __shared__ WaveLds s_wl[256 / kWave];
-        const int wave = threadIdx.x / kWave;
-        for (int t = blockIdx.x * (256 / kWave) + wave; t < T->h.mor_pre[nj]; t += gridDim.x * (256 / kWave))
-            morph_band<KMAX, NC>(T, nj, t, s_wl[wave]);
+        const int rb = 4 * J->band, H = J->H, W = J->W;
+        const int nb = (H + rb - 1) / rb, nsub = (H + J->band - 1) / J->band;
+        // classify the band once the frame's inverse gain is known
+        if (threadIdx.x == 0) {
+            spin_until(&J->ginv, 0x80000000u, false, ps, __builtin_amdgcn_s_memrealtime());
+            s_u = ld_dev(&J->ginv) & 0x7FFFFFFFu;
+        }
+        __syncthreads();
+        const uint32_t inv = s_u;
+        const uint32_t p0 = (uint32_t)(idx * rb) * (uint32_t)W;
+        const uint32_t p1 = (uint32_t)min(H, (idx + 1) * rb) * (uint32_t)W;
+        classify_span<true>(cls_job(J), p0, p1, inv);
+        wait_own_memory();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            st_dev(G(J->bflag + idx), J->epoch);
+        // the morphology of the band above, and of this band when it is the last
+        for (int m = max(0, idx - 1); m <= idx; ++m) {
+            if (m == idx && idx != nb - 1)
+                break;
+            if (threadIdx.x == 0) {
+                // its rows and halo lie in bands m - 1 .. m + 1
+                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                for (int bb = max(0, m - 1); bb <= min(nb - 1, m + 1); ++bb)
+                    if (bb != idx)
+                        spin_until(J->bflag + bb, J->epoch, true, ps, t0);
+            }
+            acquire_for_block();
+            const int sub = 4 * m + wave;
+            if (sub < nsub)
+                morph_band<KMAX, NC, true>(J, sub, s_wl[wave]);
+            const uint32_t cnt = (uint32_t)min(4, nsub - 4 * m);
+            if (publish_add(&J->morph_done, cnt, &s_u) + cnt == (uint32_t)nsub) {
+                // the frame's last band: its components
+                acquire_for_block();
+                resolve_job(T, j, true);
+            }
+        }
     }
-    ok = grid_sync(ps, 3) && ok;
-    if (ok)
-        for (int j = blockIdx.x; j < nj; j += gridDim.x)
-            resolve_job(T, j, true);
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned done = atomicAdd(&ps->finished, 1u);
         if (done == gridDim.x - 1) {
-            __hip_atomic_store(&ps->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ps->next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ps->finished, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -1383,55 +1578,39 @@ hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEve
 // allow (wave64, 512 VGPRs per SIMD lane in granules of 8, four SIMDs and
 // 160 KiB of LDS per CU, eight waves per SIMD), capped at four so that the
 // whole grid is resident with room to spare.
-template <int ITERS, int KMAX, int NC>
-int step_blocks_per_cu()
+template <int KMAX, int NC>
+int flow_blocks_per_cu()
 {
-    hipFuncAttributes a{};
-    if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(k_step<ITERS, KMAX, NC>)) != hipSuccess)
-        return 1;
-    const int vgpr = std::max(8, (a.numRegs + 7) / 8 * 8);
-    const int waves_per_simd = std::min(8, 512 / vgpr);     // one wave of each block per SIMD
-    const int by_lds = (int)((160 * 1024) / std::max<size_t>(1, a.sharedSizeBytes));
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<ITERS, KMAX, NC>, 256, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_flow<KMAX, NC>, 256, 0) != hipSuccess)
         nb = 1;
-    return std::max(1, std::min(std::min(nb, 4), std::min(waves_per_simd, by_lds)));
+    return std::max(1, std::min(nb, 8));
 }
 
-template <int ITERS, int KMAX, int NC>
-hipError_t launch_step_t(Table *tab, int n_cu, PersistState *ps, hipStream_t s, StageEvents ev)
+template <int KMAX, int NC>
+hipError_t launch_flow_t(Table *tab, int n_cu, PersistState *ps, hipStream_t s, StageEvents ev)
 {
     static int per_cu = -1;
     if (per_cu < 0)
-        per_cu = step_blocks_per_cu<ITERS, KMAX, NC>();
-    FIZI_LAUNCH((k_step<ITERS, KMAX, NC>), per_cu * n_cu, 256, 0, s, ev, tab, ps);
+        per_cu = flow_blocks_per_cu<KMAX, NC>();
+    FIZI_LAUNCH((k_flow<KMAX, NC>), per_cu * n_cu, 256, 0, s, ev, tab, ps);
     return hipGetLastError();
-}
-
-template <int ITERS>
-hipError_t launch_step_i(Table *tab, int max_wd, int max_ops, int n_cu, PersistState *ps, hipStream_t s,
-                         StageEvents ev)
-{
-    const bool wide = max_wd > kWave, deep = max_ops > 4;
-    if (!wide && !deep)
-        return launch_step_t<ITERS, 4, 1>(tab, n_cu, ps, s, ev);
-    if (!wide)
-        return launch_step_t<ITERS, 4 * kMaxMorphIters, 1>(tab, n_cu, ps, s, ev);
-    if (!deep)
-        return launch_step_t<ITERS, 4, 2>(tab, n_cu, ps, s, ev);
-    return launch_step_t<ITERS, 4 * kMaxMorphIters, 2>(tab, n_cu, ps, s, ev);
 }
 
 hipError_t launch_persistent(const Table *d_tab, int max_wd, int max_ops, int n_cu, const Tuning &t,
                              uint8_t *persist, hipStream_t s, StageEvents ev)
 {
+    (void)t;
     Table *tab = const_cast<Table *>(d_tab);
     PersistState *ps = reinterpret_cast<PersistState *>(persist);
-    switch (t.cls_iters) {
-    case 2: return launch_step_i<2>(tab, max_wd, max_ops, n_cu, ps, s, ev);
-    case 8: return launch_step_i<8>(tab, max_wd, max_ops, n_cu, ps, s, ev);
-    default: return launch_step_i<4>(tab, max_wd, max_ops, n_cu, ps, s, ev);
-    }
+    const bool wide = max_wd > kWave, deep = max_ops > 4;
+    if (!wide && !deep)
+        return launch_flow_t<4, 1>(tab, n_cu, ps, s, ev);
+    if (!wide)
+        return launch_flow_t<4 * kMaxMorphIters, 1>(tab, n_cu, ps, s, ev);
+    if (!deep)
+        return launch_flow_t<4, 2>(tab, n_cu, ps, s, ev);
+    return launch_flow_t<4 * kMaxMorphIters, 2>(tab, n_cu, ps, s, ev);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s)
