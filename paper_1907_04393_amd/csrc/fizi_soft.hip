@@ -20,9 +20,12 @@ struct SoftParams {
 };
 
 struct SoftPx {
-    float m, z, d, ub, ur;
+    float m, z, d, h, e, ub, ur;   // h = 1 / (2 d) (0 at d = 0), e = exp(-|z|)
 };
 
+// Three transcendentals per pixel: one reciprocal square root gives d and
+// 1 / (2 d), one exponential gives the sigmoid (and the BCE's softplus), one
+// reciprocal.
 __device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftParams &s)
 {
     const float cb = fmaf(0.5f, b, fmaf(-0.331264f, g, fmaf(-0.168736f, r, 128.0f)));
@@ -31,9 +34,14 @@ __device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftP
     SoftPx o;
     o.ub = fmaf(s.p_bb, db, s.p_br * dr);
     o.ur = fmaf(s.p_br, db, s.p_rr * dr);
-    o.d = sqrtf(fmaxf(fmaf(db, o.ub, dr * o.ur), 0.0f));
+    const float q = fmaxf(fmaf(db, o.ub, dr * o.ur), 0.0f);
+    const float rs = q > 0.0f ? __frsqrt_rn(q) : 0.0f;
+    o.d = q * rs;
+    o.h = 0.5f * rs;
     o.z = (s.theta - o.d) * s.inv_t;
-    o.m = __frcp_rn(1.0f + __expf(-o.z));   // hardware exp2 / reciprocal, ~1 ulp
+    o.e = __expf(-fabsf(o.z));
+    const float rc = __frcp_rn(1.0f + o.e);
+    o.m = o.z >= 0.0f ? rc : o.e * rc;
     return o;
 }
 
@@ -64,31 +72,51 @@ __global__ __launch_bounds__(256) void k_soft_fwd(const uint8_t *__restrict__ fr
     }
 }
 
-// Adds one pixel's contributions (FP32) to acc: dL/dz is gz.
+// Adds one pixel's contributions (FP32) to acc: dL/dz is gz. With
+// g = -dL/dq = gz / (2 T d) and u = S^-1 delta: dL/dmu = 2 g u, dL/dS =
+// g u u^T (the off-diagonal entry counted twice) and dL/dtheta = gz / T; the
+// constant factors (2, 2, 1, 2, 1, 1/T) are applied once, to the final sums.
 __device__ __forceinline__ void soft_acc(const SoftPx &o, float gz, float inv_t, float *acc)
 {
-    const float gd = -gz * inv_t;
-    const float gq = o.d > 0.0f ? gd * __frcp_rn(2.0f * o.d) : 0.0f;
-    acc[0] += gq * (-2.0f * o.ub);
-    acc[1] += gq * (-2.0f * o.ur);
-    acc[2] += gq * (-o.ub * o.ub);
-    acc[3] += gq * (-2.0f * o.ub * o.ur);
-    acc[4] += gq * (-o.ur * o.ur);
-    acc[5] += gz * inv_t;
+    const float gq = gz * inv_t * o.h;     // -dL/dq
+    const float a = gq * o.ub, b = gq * o.ur;
+    acc[0] += a;
+    acc[1] += b;
+    acc[2] = fmaf(a, o.ub, acc[2]);
+    acc[3] = fmaf(a, o.ur, acc[3]);
+    acc[4] = fmaf(b, o.ur, acc[4]);
+    acc[5] += gz;
 }
 
-// dL/dz of one pixel: from the upstream dL/dm, or (fused BCE) (m - y) / N,
-// which also adds the pixel's BCE term to acc[6].
-__device__ __forceinline__ float soft_gz(const SoftPx &o, const float *dLdm, const uint8_t *gt, long long i,
-                                         float inv_n, float *acc)
+// dL/dz of one pixel from the upstream dL/dm.
+__device__ __forceinline__ float gz_upstream(const SoftPx &o, float dm) { return dm * o.m * (1.0f - o.m); }
+
+// Fused BCE: dL/dz = (m - y) / N, and the pixel's BCE term is added to acc[6].
+__device__ __forceinline__ float gz_bce(const SoftPx &o, uint32_t y8, float inv_n, float *acc)
 {
-    if (dLdm)
-        return dLdm[i] * o.m * (1.0f - o.m);
-    const float y = gt[i] ? 1.0f : 0.0f;
-    acc[6] += fmaxf(o.z, 0.0f) - o.z * y + __logf(1.0f + __expf(-fabsf(o.z)));
+    const float y = y8 ? 1.0f : 0.0f;
+    acc[6] += fmaxf(o.z, 0.0f) - o.z * y + __logf(1.0f + o.e);
     return (o.m - y) * inv_n;
 }
 
+// One group of 4 pixels (3 frame dwords) with its upstream gradients (dm) or
+// ground-truth bytes (y4), added to acc in FP32.
+template <bool BCE>
+__device__ __forceinline__ void soft_group(uint32_t w0, uint32_t w1, uint32_t w2, const float *dm, uint32_t y4,
+                                           const SoftParams &s, float inv_n, float *acc)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const SoftPx o = soft_px(byte_at(w0, w1, w2, 3 * k), byte_at(w0, w1, w2, 3 * k + 1),
+                                 byte_at(w0, w1, w2, 3 * k + 2), s);
+        const float gz = BCE ? gz_bce(o, (y4 >> (8 * k)) & 0xFFu, inv_n, acc) : gz_upstream(o, dm[k]);
+        soft_acc(o, gz, s.inv_t, acc);
+    }
+}
+
+// VEC: dL/dm is 16-byte and the ground truth 4-byte aligned, so a group's
+// four values come in one load.
+template <bool BCE, bool VEC>
 __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ frames, const float *__restrict__ dLdm,
                                                   const uint8_t *__restrict__ gt, long long npx, SoftParams s,
                                                   float inv_n, double *__restrict__ partial)
@@ -97,25 +125,58 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ fr
     double acc[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};
     const long long groups = npx / 4;
     const uint32_t *f = reinterpret_cast<const uint32_t *>(frames);
-    for (long long gi = blockIdx.x * (long long)blockDim.x + threadIdx.x; gi < groups;
-         gi += (long long)gridDim.x * blockDim.x) {
-        const uint32_t w0 = f[3 * gi], w1 = f[3 * gi + 1], w2 = f[3 * gi + 2];
-        float a4[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};   // the 4 pixels in FP32
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    // groups gi and gi + stride together: their loads in flight at once, their
+    // 8 pixels summed in FP32 before the FP64 accumulators
+    for (long long g0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; g0 < groups; g0 += 2 * stride) {
+        uint32_t w[2][3];
+        float dm[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+        uint32_t y4[2] = {0, 0};
+        bool have[2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const SoftPx o = soft_px(byte_at(w0, w1, w2, 3 * k), byte_at(w0, w1, w2, 3 * k + 1),
-                                     byte_at(w0, w1, w2, 3 * k + 2), s);
-            soft_acc(o, soft_gz(o, dLdm, gt, 4 * gi + k, inv_n, a4), s.inv_t, a4);
+        for (int u = 0; u < 2; ++u) {
+            const long long gi = g0 + u * stride;
+            have[u] = gi < groups;
+            if (!have[u])
+                continue;
+            w[u][0] = f[3 * gi];
+            w[u][1] = f[3 * gi + 1];
+            w[u][2] = f[3 * gi + 2];
+            if (BCE) {
+                if (VEC) {
+                    y4[u] = reinterpret_cast<const uint32_t *>(gt)[gi];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        y4[u] |= (uint32_t)gt[4 * gi + k] << (8 * k);
+                }
+            } else if (VEC) {
+                const float4 v = reinterpret_cast<const float4 *>(dLdm)[gi];
+                dm[u][0] = v.x;
+                dm[u][1] = v.y;
+                dm[u][2] = v.z;
+                dm[u][3] = v.w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    dm[u][k] = dLdm[4 * gi + k];
+            }
         }
+        float a8[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};   // up to 8 pixels in FP32
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (have[u])
+                soft_group<BCE>(w[u][0], w[u][1], w[u][2], dm[u], y4[u], s, inv_n, a8);
 #pragma unroll
         for (int k = 0; k < kSoftOut - 1; ++k)
-            acc[k] += (double)a4[k];
+            acc[k] += (double)a8[k];
     }
     if (blockIdx.x == 0 && threadIdx.x < (unsigned)(npx - 4 * groups)) {
         const long long i = 4 * groups + threadIdx.x;
         float a1[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};
         const SoftPx o = soft_px(frames[3 * i], frames[3 * i + 1], frames[3 * i + 2], s);
-        soft_acc(o, soft_gz(o, dLdm, gt, i, inv_n, a1), s.inv_t, a1);
+        const float gz = BCE ? gz_bce(o, gt[i], inv_n, a1) : gz_upstream(o, dLdm[i]);
+        soft_acc(o, gz, s.inv_t, a1);
         for (int k = 0; k < kSoftOut - 1; ++k)
             acc[k] += (double)a1[k];
     }
@@ -137,8 +198,12 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ fr
     }
 }
 
+struct SoftScale {
+    double k[kSoftOut];
+};
+
 // Fixed-order sum of the block partials: out[k] = sum_b partial[b][k] * scale[k].
-__global__ __launch_bounds__(256) void k_soft_final(const double *__restrict__ partial, int nblocks, double loss_scale,
+__global__ __launch_bounds__(256) void k_soft_final(const double *__restrict__ partial, int nblocks, SoftScale scale,
                                                     double *__restrict__ out, int nout)
 {
     __shared__ double s[256];
@@ -154,7 +219,7 @@ __global__ __launch_bounds__(256) void k_soft_final(const double *__restrict__ p
             __syncthreads();
         }
         if (threadIdx.x == 0)
-            out[k] = k == 6 ? s[0] * loss_scale : s[0];
+            out[k] = s[0] * scale.k[k];
         __syncthreads();
     }
 }
@@ -204,9 +269,22 @@ int soft_backward(const uint8_t *frames, const float *dLdm, const uint8_t *gt, l
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int grid = soft_grid(npx);
     double *partial = static_cast<double *>(ws);
-    k_soft_bwd<<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, (float)(1.0 / (double)npx), partial);
+    const float inv_n = (float)(1.0 / (double)npx);
+    if (gt) {
+        if (reinterpret_cast<uintptr_t>(gt) % 4 == 0)
+            k_soft_bwd<true, true><<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, inv_n, partial);
+        else
+            k_soft_bwd<true, false><<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, inv_n, partial);
+    } else {
+        if (reinterpret_cast<uintptr_t>(dLdm) % 16 == 0)
+            k_soft_bwd<false, true><<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, inv_n, partial);
+        else
+            k_soft_bwd<false, false><<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, inv_n, partial);
+    }
     FIZI_HIP(hipGetLastError());
-    k_soft_final<<<1, 256, 0, st>>>(partial, grid, 1.0 / (double)npx, out, nout);
+    // dL/dmu_b, dL/dmu_r, dL/ds_bb, dL/ds_br, dL/ds_rr, dL/dtheta, loss
+    const SoftScale scale{{2.0, 2.0, 1.0, 2.0, 1.0, (double)s.inv_t, 1.0 / (double)npx, 0.0}};
+    k_soft_final<<<1, 256, 0, st>>>(partial, grid, scale, out, nout);
     FIZI_HIP(hipGetLastError());
     return FIZI_OK;
 }
