@@ -142,7 +142,11 @@ int fizi_state_layout(const fizi_geom *geom, const fizi_params *params, int32_t 
 int fizi_create(const fizi_geom *geom, const fizi_params *params, int32_t chunk_frames,
                 void *d_state, size_t state_bytes, void *stream, fizi_ctx **out);
 
-/* Section 2 initialisation ("learns the background without the user") with
+/* Frames everywhere below are H x W x 3 uint8, interleaved RGB, row-major,
+ * consecutive frames contiguous, in device memory, 4-byte aligned
+ * (FIZI_EINVAL otherwise; 16-byte aligned frames take the faster gain path).
+ *
+ * Section 2 initialisation ("learns the background without the user") with
  * the model of Section 3.1 (i): with reset != 0 the reference luminance is
  * taken from d_frames[0] and the per-pixel, per-channel [bgmin, bgmax] model
  * starts empty; otherwise learning continues from the current model. Each

@@ -204,6 +204,8 @@ int fizi_batch_learn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, 
 {
     if (!b || !d_frames)
         return fail(FIZI_EINVAL, "null batch or frames");
+    if (reinterpret_cast<uintptr_t>(d_frames) % 4 != 0)
+        return fail(FIZI_EINVAL, "frames must be 4-byte aligned");
     if (stream_id < 0 || stream_id >= b->n)
         return fail(FIZI_EINVAL, "stream_id out of range");
     if (n_frames < 1)
@@ -239,9 +241,12 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
     if (!b || !h_frames || !d_pointers)
         return fail(FIZI_EINVAL, "null batch, frame array or pointer array");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int i = 0; i < b->n; ++i)
+    for (int i = 0; i < b->n; ++i) {
         if (h_frames[i] && !b->m[i].learned)
             return fail(FIZI_ESTATE, "a stream in the step has no learned background");
+        if (reinterpret_cast<uintptr_t>(h_frames[i]) % 4 != 0)
+            return fail(FIZI_EINVAL, "frames must be 4-byte aligned");
+    }
     FIZI_TRY(order_after_previous(b, s));
     int slot;
     FIZI_TRY(b->ring.take(&slot));

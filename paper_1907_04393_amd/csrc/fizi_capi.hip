@@ -192,6 +192,8 @@ int learn_background(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, int
 {
     if (!c || !d_frames)
         return fail(FIZI_EINVAL, "null context or frames");
+    if (reinterpret_cast<uintptr_t>(d_frames) % 4 != 0)
+        return fail(FIZI_EINVAL, "frames must be 4-byte aligned");
     if (n_frames < 1)
         return fail(FIZI_EINVAL, "n_frames must be >= 1");
     if (!reset && !c->m.learned)
@@ -207,6 +209,8 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
 {
     if (!c || !d_frames)
         return fail(FIZI_EINVAL, "null context or frames");
+    if (reinterpret_cast<uintptr_t>(d_frames) % 4 != 0)
+        return fail(FIZI_EINVAL, "frames must be 4-byte aligned");
     if (n_frames < 1)
         return fail(FIZI_EINVAL, "n_frames must be >= 1");
     if (!c->m.learned)

@@ -228,6 +228,47 @@ __device__ __forceinline__ void gain_tile(Table *__restrict__ T, int j, int tile
     const HueTest h = J->hue;
     uint32_t num = 0, den = 0;
     const int r0 = tile * kGainRows, nr = min(rows, r0 + kGainRows) - r0;
+    // one usable-pixel test, summed into num/den
+    auto add_px = [&](uint32_t r, uint32_t gg, uint32_t b, uint32_t y) {
+        bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
+        if (ok) {
+            const int mx = max(max((int)r, (int)gg), (int)b);
+            const int mn = min(min((int)r, (int)gg), (int)b);
+            if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
+                ok = false;
+        }
+        if (ok) {
+            num += y;
+            den += r + 2 * gg + b;
+        }
+    };
+    if ((reinterpret_cast<uintptr_t>(J->frame) & 15u) == 0) {
+        // 16 pixels per item: three 16-byte loads of the frame row, two of
+        // the reference row; items of the tile's rows in one flat range
+        const int n16 = W / 16;
+        const uint8_t *frame = J->frame;
+        const uint16_t *yref = J->yref;
+        const size_t rowb = (size_t)J->rs * W * 3;
+#pragma unroll 2
+        for (int it = threadIdx.x; it < nr * n16; it += blockDim.x) {
+            int row = 0;
+#pragma unroll
+            for (int q = 1; q < kGainRows; ++q)
+                row += it >= q * n16;
+            const int g = it - row * n16, rr = r0 + row;
+            const uint4 *fp = reinterpret_cast<const uint4 *>(frame + (size_t)rr * rowb) + 3 * g;
+            const uint4 *yp = reinterpret_cast<const uint4 *>(yref + (size_t)rr * W) + 2 * g;
+            const uint4 a = fp[0], b = fp[1], c = fp[2], ya = yp[0], yb = yp[1];
+            const uint32_t fw[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+            const uint32_t yw[8] = {ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w};
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int q0 = 3 * k;
+                add_px((fw[q0 >> 2] >> (8 * (q0 & 3))) & 0xFFu, (fw[(q0 + 1) >> 2] >> (8 * ((q0 + 1) & 3))) & 0xFFu,
+                       (fw[(q0 + 2) >> 2] >> (8 * ((q0 + 2) & 3))) & 0xFFu, (yw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
+            }
+        }
+    } else {
     const int groups = W / 4;
 #pragma unroll 4
     for (int it = threadIdx.x; it < nr * groups; it += blockDim.x) {
@@ -240,19 +281,9 @@ __device__ __forceinline__ void gain_tile(Table *__restrict__ T, int j, int tile
         for (int k = 0; k < 4; ++k) {
             const uint32_t r = byte_of(w0, w1, w2, 3 * k), gg = byte_of(w0, w1, w2, 3 * k + 1),
                            b = byte_of(w0, w1, w2, 3 * k + 2);
-            const uint32_t y = (uint32_t)(yv >> (16 * k)) & 0xFFFFu;
-            bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
-            if (ok) {
-                const int mx = max(max((int)r, (int)gg), (int)b);
-                const int mn = min(min((int)r, (int)gg), (int)b);
-                if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
-                    ok = false;
-            }
-            if (ok) {
-                num += y;
-                den += r + 2 * gg + b;
-            }
+            add_px(r, gg, b, (uint32_t)(yv >> (16 * k)) & 0xFFFFu);
         }
+    }
     }
     num = wave_sum(num);
     den = wave_sum(den);

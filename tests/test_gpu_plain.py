@@ -231,3 +231,44 @@ def test_determinism():
     b = gpu_run(bg, hand[:16], {}, chunk=5)
     assert a["pointers"] == b["pointers"]
     assert np.array_equal(a["fizi"], b["fizi"]) and np.array_equal(a["hand"], b["hand"])
+
+
+def _offset_copy(t, offset, dev):
+    """t copied to device memory that starts `offset` bytes past an aligned
+    allocation."""
+    flat = t.reshape(-1)
+    buf = torch.zeros(flat.numel() + 64, dtype=torch.uint8, device=dev)
+    buf[offset:offset + flat.numel()] = flat.to(dev)
+    return buf[offset:offset + flat.numel()].view(t.shape)
+
+
+def test_word_aligned_frames_match_oracle():
+    """Frames 4-byte but not 16-byte aligned take the per-word gain path;
+    results are the same."""
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    bg, hand = _blob_scene(192, 70, 6, 5, seed=1234)
+    ctx = fizi.Context(192, 70, chunk=3, device=dev)
+    ctx.learn_background(_offset_copy(bg, 4, dev))
+    out = ctx.process_frames(_offset_copy(hand, 4, dev), want_fizi=True)
+    torch.cuda.synchronize()
+    m, outs = oracle_run(bg, hand, {})
+    got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(out["pointers"])]
+    bits = fizi.unpack_bits(out["fizi"], 192)
+    for k, o in outs.items():
+        assert got[k] == o["pointer"], k
+        assert np.array_equal(bits[k], o["fizi"]), k
+
+
+def test_unaligned_frames_are_rejected():
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    bg, hand = _blob_scene(64, 8, 2, 1, seed=5)
+    ctx = fizi.Context(64, 8, chunk=1, device=dev)
+    with pytest.raises(fizi.FiziError) as e:
+        ctx.learn_background(_offset_copy(bg, 1, dev))
+    assert e.value.code == fizi.FIZI_EINVAL
+    ctx.learn_background(bg.to(dev))
+    with pytest.raises(fizi.FiziError) as e:
+        ctx.process_frames(_offset_copy(hand, 2, dev))
+    assert e.value.code == fizi.FIZI_EINVAL
