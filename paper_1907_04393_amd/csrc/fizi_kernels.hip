@@ -1220,7 +1220,7 @@ __global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T)
 }
 
 // ---------------------------------------------------------------------------
-constexpr int kResolveThreads = 512;
+constexpr int kResolveThreads = 1024;
 constexpr int kMaxWaves = 16;
 
 template <typename T, typename Op>
