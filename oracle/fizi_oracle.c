@@ -32,7 +32,9 @@
  *   R7  the hand zone = the 8-connected component of largest area, ties going
  *       to the smallest first raster index (Section 2, Mouse module);
  *   R8  the pointer = area, coordinate sums, bounding box and a fill-ratio
- *       click (Section 2 "its movement, its state (click or not)").
+ *       click (Section 2 "its movement, its state (click or not)");
+ *   R9  partial re-learning (Section 3.3) widens the model with running
+ *       frames at the pixels their I_FIZI marks as background.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -197,6 +199,46 @@ int orc_learn(const uint8_t *frames, int n, int W, int H, const orc_params *p, i
                 bgmin[i] = tmp[i];
             if (tmp[i] > bgmax[i])
                 bgmax[i] = tmp[i];
+        }
+    }
+    free(tmp);
+    return 0;
+}
+
+/* ---- Section 3.3: partial re-learning --------------------------------------
+ * "Dealing with the evolution of the luminosity implies sometimes to
+ * re-initiate partly the machine learning" (Section 3.3). Reading R9: frames
+ * seen while running widen the learned model exactly as learning frames do
+ * (gain-corrected against the same reference luminance, per-channel min and
+ * max), but only at the pixels the frame's I_FIZI marks as background
+ * (fizi[k][i] == 0): the hand zone never enters the model. The reference
+ * luminance is unchanged. fizi: n frames of W*H bytes, 0 or 1. */
+int orc_relearn(const uint8_t *frames, const uint8_t *fizi, int n, int W, int H, const orc_params *p,
+                uint8_t *bgmin, uint8_t *bgmax, const uint16_t *yref, uint32_t *inv_out)
+{
+    size_t npx = (size_t)W * H;
+    uint8_t *tmp;
+    if (n < 0)
+        return -1;
+    tmp = (uint8_t *)malloc(npx * 3);
+    if (!tmp)
+        return -2;
+    for (int k = 0; k < n; k++) {
+        const uint8_t *F = frames + (size_t)k * npx * 3;
+        const uint8_t *M = fizi + (size_t)k * npx;
+        uint32_t inv = orc_gain(F, yref, W, H, p);
+        if (inv_out)
+            inv_out[k] = inv;
+        orc_correct(F, inv, npx * 3, tmp);
+        for (size_t i = 0; i < npx; i++) {
+            if (M[i])
+                continue;
+            for (int c = 0; c < 3; c++) {
+                if (tmp[i * 3 + c] < bgmin[i * 3 + c])
+                    bgmin[i * 3 + c] = tmp[i * 3 + c];
+                if (tmp[i * 3 + c] > bgmax[i * 3 + c])
+                    bgmax[i * 3 + c] = tmp[i * 3 + c];
+            }
         }
     }
     free(tmp);

@@ -72,6 +72,8 @@ def lib():
         L.orc_correct.argtypes = [u8p, ctypes.c_uint32, ctypes.c_size_t, u8p]
         L.orc_learn.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(Params), ctypes.c_int,
                                 u8p, u8p, P(ctypes.c_uint16), P(ctypes.c_uint32)]
+        L.orc_relearn.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(Params), u8p, u8p,
+                                  P(ctypes.c_uint16), P(ctypes.c_uint32)]
         L.orc_masks.argtypes = [u8p, u8p, u8p, ctypes.c_size_t, P(Params), u8p, u8p, u8p, u8p]
         L.orc_erode.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int]
         L.orc_dilate.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int]
@@ -169,6 +171,24 @@ class Model:
         if rc != 0:
             raise ValueError(f"orc_learn failed ({rc})")
         self.learned = True
+        return inv[:n]
+
+    def relearn(self, frames, fizi):
+        """Partial re-learning (Section 3.3, reading R9): widen the model with
+        frames (n, H, W, 3) at the pixels where fizi (n, H, W, 0/1) is 0."""
+        if not self.learned:
+            raise ValueError("relearn needs a learned model")
+        f = _c(frames, np.uint8)
+        m = _c((np.asarray(fizi) != 0).astype(np.uint8), np.uint8)
+        n = f.shape[0]
+        assert m.shape == (n, self.H, self.W)
+        inv = np.zeros(max(n, 1), np.uint32)
+        rc = lib().orc_relearn(_u8(f), _u8(m), n, self.W, self.H, ctypes.byref(self.p),
+                               _u8(self.bgmin), _u8(self.bgmax),
+                               self.yref.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                               inv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+        if rc != 0:
+            raise ValueError(f"orc_relearn failed ({rc})")
         return inv[:n]
 
     def process(self, frame, frame_index=0, want_raw=False, want_hand=False):
