@@ -196,9 +196,32 @@ def bench_learn(args, torch, fizi, scene):
     ms, launches = ctx.stage_times()["learn"]
     k_s = ms / 1e3 / max(1, launches)
     byts = W * H * (3 * n + 12)
-    return {"workload": f"{n} frames 1920x1080 per call", "ms_per_call": round(sec * 1e3, 3),
-            "frames_per_s": round(n / sec, 1), "minmax_kernel_us": round(k_s * 1e6, 1),
-            "minmax_GBps": round(byts / k_s / 1e9, 1), "minmax_frac": round(byts / k_s / 1e9 / HBM_PEAK_GBS, 4)}
+    out = {"workload": f"{n} frames 1920x1080 per call", "ms_per_call": round(sec * 1e3, 3),
+           "frames_per_s": round(n / sec, 1), "minmax_kernel_us": round(k_s * 1e6, 1),
+           "minmax_GBps": round(byts / k_s / 1e9, 1), "minmax_frac": round(byts / k_s / 1e9 / HBM_PEAK_GBS, 4)}
+    # partial re-learning: running frames fed back with their I_FIZI masks
+    # (model 12 B/px once per call, each frame 3 B/px + its mask 1/8 B/px)
+    hand = scene.Scene(spec, device=dev).hand_frames(0, 8)
+    bits = ctx.process_frames(hand, want_fizi=True)["fizi"]
+    torch.cuda.synchronize()
+    ctx.stage_times()
+    for k in (1, 8):
+        ctx.relearn_background(hand[:k], bits[:k])
+        torch.cuda.synchronize()
+        ctx.stage_times()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.relearn_background(hand[:k], bits[:k])
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        ms, launches = ctx.stage_times()["learn"]
+        k_s = ms / 1e3 / max(1, launches)
+        byts = W * H * ((3 + 1 / 8) * k + 12)
+        out[f"relearn_{k}_frames"] = {"ms_per_call": round(sec * 1e3, 3), "kernel_us": round(k_s * 1e6, 1),
+                                      "GBps": round(byts / k_s / 1e9, 1),
+                                      "frac": round(byts / k_s / 1e9 / HBM_PEAK_GBS, 4)}
+    ctx.stage_timing(False)
+    return out
 
 
 def bench_soft(args, torch, scene):

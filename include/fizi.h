@@ -155,6 +155,18 @@ int fizi_create(const fizi_geom *geom, const fizi_params *params, int32_t chunk_
 int learn_background(fizi_ctx *ctx, const uint8_t *d_frames, int32_t n_frames, int32_t reset,
                      void *stream);
 
+/* Section 3.3 partial re-learning ("dealing with the evolution of the
+ * luminosity implies sometimes to re-initiate partly the machine learning"):
+ * n_frames >= 1 running frames widen the model exactly as learning frames do
+ * (gain-corrected against the unchanged reference luminance, per-channel min
+ * and max), but only at the pixels whose bit in that frame's I_FIZI mask
+ * (d_fizi_bits: n_frames masks of H rows of W/64 words, as process_frames
+ * writes them; 8-byte aligned) is 0, so the hand zone never enters the model.
+ * The caller chooses which frames to feed back. FIZI_ESTATE before the first
+ * learn_background. Async, ordered after the context's earlier calls. */
+int relearn_background(fizi_ctx *ctx, const uint8_t *d_frames, int32_t n_frames,
+                       const uint64_t *d_fizi_bits, void *stream);
+
 /* Section 2 running phase for n_frames >= 1 frames: brightness correction,
  * the masks I_R1, I_R2, I_R3 of Section 3.1 and their AND, opening and
  * closing (I_FIZI), the hand zone and its pointer. Frames are independent
@@ -217,6 +229,10 @@ int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_para
 /* learn_background for one stream of the batch. Async. */
 int fizi_batch_learn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, int32_t n_frames,
                      int32_t reset, void *stream);
+
+/* relearn_background for stream stream_id of the batch. */
+int fizi_batch_relearn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, int32_t n_frames,
+                       const uint64_t *d_fizi_bits, void *stream);
 
 /* One frame step. h_frames: host array of n_streams device frame pointers,
  * NULL for a stream with no frame this step. h_fizi_bits: NULL, or a host

@@ -219,6 +219,26 @@ int fizi_batch_learn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, 
     return mark_last(b, s);
 }
 
+int fizi_batch_relearn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, int32_t n_frames,
+                       const uint64_t *d_fizi_bits, void *stream)
+{
+    if (!b || !d_frames || !d_fizi_bits)
+        return fail(FIZI_EINVAL, "null batch, frames or masks");
+    if (reinterpret_cast<uintptr_t>(d_frames) % 4 != 0 || reinterpret_cast<uintptr_t>(d_fizi_bits) % 8 != 0)
+        return fail(FIZI_EINVAL, "frames must be 4-byte and masks 8-byte aligned");
+    if (stream_id < 0 || stream_id >= b->n)
+        return fail(FIZI_EINVAL, "stream_id out of range");
+    if (n_frames < 1)
+        return fail(FIZI_EINVAL, "n_frames must be >= 1");
+    Model &m = b->m[stream_id];
+    if (!m.learned)
+        return fail(FIZI_ESTATE, "relearning needs a learned model");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FIZI_TRY(order_after_previous(b, s));
+    FIZI_TRY(learn_model(m, b->ring, b->tune, b->n_cu, d_frames, n_frames, 0, s, &b->clk, d_fizi_bits));
+    return mark_last(b, s);
+}
+
 int fizi_batch_set_mode(fizi_batch *b, int32_t mode)
 {
     if (!b)

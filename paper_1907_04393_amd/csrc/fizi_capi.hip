@@ -204,6 +204,23 @@ int learn_background(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, int
     return mark_last(c, s);
 }
 
+int relearn_background(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, const uint64_t *d_fizi_bits,
+                       void *stream)
+{
+    if (!c || !d_frames || !d_fizi_bits)
+        return fail(FIZI_EINVAL, "null context, frames or masks");
+    if (reinterpret_cast<uintptr_t>(d_frames) % 4 != 0 || reinterpret_cast<uintptr_t>(d_fizi_bits) % 8 != 0)
+        return fail(FIZI_EINVAL, "frames must be 4-byte and masks 8-byte aligned");
+    if (n_frames < 1)
+        return fail(FIZI_EINVAL, "n_frames must be >= 1");
+    if (!c->m.learned)
+        return fail(FIZI_ESTATE, "relearn_background before learn_background");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FIZI_TRY(order_after_previous(c, s));
+    FIZI_TRY(learn_model(c->m, c->ring, c->tune, c->n_cu, d_frames, n_frames, 0, s, &c->clk, d_fizi_bits));
+    return mark_last(c, s);
+}
+
 int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint64_t *d_fizi_bits,
                    uint64_t *d_hand_bits, fizi_pointer *d_pointers, void *stream)
 {

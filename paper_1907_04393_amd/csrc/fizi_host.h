@@ -109,8 +109,10 @@ int device_cu_count(int *device, int *n_cu);
 
 // Background learning of one stream from n frames (reset: reference from
 // frames[0], model starts empty).
+// Learning (and, with masks, partial re-learning: n I_FIZI bit masks whose
+// set bits keep a frame's pixels out of the model).
 int learn_model(Model &m, TableRing &ring, const Tuning &t, int n_cu, const uint8_t *frames, int n,
-                int reset, hipStream_t s, StageClock *clk);
+                int reset, hipStream_t s, StageClock *clk, const uint64_t *masks = nullptr);
 
 // Enqueues gain, classify, morphology and components for the jobs of the
 // table in device memory. With fixed_grid the launch shapes do not depend on

@@ -342,7 +342,7 @@ int device_cu_count(int *device, int *n_cu)
 }
 
 int learn_model(Model &m, TableRing &ring, const Tuning &t, int n_cu, const uint8_t *frames, int n,
-                int reset, hipStream_t s, StageClock *clk)
+                int reset, hipStream_t s, StageClock *clk, const uint64_t *masks)
 {
     const size_t px = (size_t)m.g.width * m.g.height;
     if (reset)
@@ -355,12 +355,14 @@ int learn_model(Model &m, TableRing &ring, const Tuning &t, int n_cu, const uint
         for (int i = 0; i < k; ++i) {
             fill_job(m, t.morph_rows, T.jobs[i]);
             T.jobs[i].frame = frames + (size_t)(f0 + i) * px * 3;
+            if (masks)
+                T.jobs[i].fizi = const_cast<uint64_t *>(masks) + (size_t)(f0 + i) * (px / 64);
         }
         set_prefixes(T, k, t);
         FIZI_HIP(hipMemcpyAsync(ring.d[slot], &T, table_bytes(k), hipMemcpyHostToDevice, s));
         FIZI_HIP(launch_gain(ring.d[slot], T.h.gain_pre[k], n_cu, t, s));
         FIZI_HIP(launch_minmax(ring.d[slot], k, m.bgmin, m.bgmax, (int)px, (reset && f0 == 0) ? 1 : 0,
-                               n_cu, s, clk ? clk->next(FIZI_STAGE_LEARN) : StageEvents{}));
+                               masks != nullptr, n_cu, s, clk ? clk->next(FIZI_STAGE_LEARN) : StageEvents{}));
         FIZI_TRY(ring.finish(slot, s));
     }
     m.learned = true;

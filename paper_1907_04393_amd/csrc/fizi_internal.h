@@ -131,7 +131,7 @@ hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H,
 hipError_t launch_gain(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t,
                        hipStream_t s, StageEvents ev = {});
 hipError_t launch_minmax(const Table *d_tab, int njobs, uint8_t *bgmin, uint8_t *bgmax,
-                         int npx, int reset, int n_cu, hipStream_t s, StageEvents ev = {});
+                         int npx, int reset, bool masked, int n_cu, hipStream_t s, StageEvents ev = {});
 hipError_t launch_classify(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t,
                            hipStream_t s, StageEvents ev = {});
 hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max_ops, int n_cu,

@@ -330,6 +330,8 @@ __global__ __launch_bounds__(256) void k_gain(Table *__restrict__ T)
 }
 
 // ---------------------------------------------------------------------------
+// MASKED: partial re-learning, each job's I_FIZI bits keep its pixels out.
+template <bool MASKED>
 __global__ __launch_bounds__(256) void k_minmax(Table *__restrict__ T, int nj,
                                                 uint8_t *__restrict__ bgmin,
                                                 uint8_t *__restrict__ bgmax, int npx, int reset)
@@ -362,11 +364,16 @@ __global__ __launch_bounds__(256) void k_minmax(Table *__restrict__ T, int nj,
             const GLOBAL uint32_t *f = G(reinterpret_cast<const uint32_t *>(T->jobs[j].frame)) + 3 * g;
             const uint32_t inv = s_inv[j];
             const uint32_t w0 = f[0], w1 = f[1], w2 = f[2];
+            // partial re-learning: the frame's I_FIZI (bit set = not background)
+            // excludes its pixels; plain learning has no mask
+            const uint32_t skip =
+                MASKED ? (uint32_t)(G(T->jobs[j].fizi)[g >> 4] >> ((g & 15) << 2)) & 0xFu : 0u;
 #pragma unroll
             for (int i = 0; i < 12; ++i) {
                 const uint32_t v = corr(byte_of(w0, w1, w2, i), inv);
-                lo[i] = min(lo[i], v);
-                hi[i] = max(hi[i], v);
+                const bool use = !MASKED || !((skip >> (i / 3)) & 1u);
+                lo[i] = use ? min(lo[i], v) : lo[i];
+                hi[i] = use ? max(hi[i], v) : hi[i];
             }
         }
         uint32_t a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
@@ -1552,12 +1559,16 @@ hipError_t launch_gain(const Table *d_tab, int total_tiles, int n_cu, const Tuni
 }
 
 hipError_t launch_minmax(const Table *d_tab, int njobs, uint8_t *bgmin, uint8_t *bgmax, int npx,
-                         int reset, int n_cu, hipStream_t s, StageEvents ev)
+                         int reset, bool masked, int n_cu, hipStream_t s, StageEvents ev)
 {
     const int groups = npx / 4;
     const int grid = min((groups + 255) / 256, n_cu * 8);
-    FIZI_LAUNCH(k_minmax, grid, 256, 0, s, ev, const_cast<Table *>(d_tab), njobs, bgmin, bgmax, npx,
-                reset);
+    if (masked)
+        FIZI_LAUNCH(k_minmax<true>, grid, 256, 0, s, ev, const_cast<Table *>(d_tab), njobs, bgmin, bgmax, npx,
+                    reset);
+    else
+        FIZI_LAUNCH(k_minmax<false>, grid, 256, 0, s, ev, const_cast<Table *>(d_tab), njobs, bgmin, bgmax, npx,
+                    reset);
     return hipGetLastError();
 }
 

@@ -88,6 +88,7 @@ def lib():
     L.fizi_state_layout.argtypes = [P(Geom), P(Params), i32, P(Layout)]
     L.fizi_create.argtypes = [P(Geom), P(Params), i32, vp, ctypes.c_size_t, vp, P(vp)]
     L.learn_background.argtypes = [vp, vp, i32, i32, vp]
+    L.relearn_background.argtypes = [vp, vp, i32, vp, vp]
     L.process_frames.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     L.get_pointer.argtypes = [vp, i64, P(PointerC)]
     L.fizi_destroy.argtypes = [vp]
@@ -106,6 +107,7 @@ def _extra_signatures(L):
         L.fizi_batch_state_bytes.restype = ctypes.c_size_t
         L.fizi_batch_create.argtypes = [i32, P(Geom), P(Params), vp, ctypes.c_size_t, P(vp)]
         L.fizi_batch_learn.argtypes = [vp, i32, vp, i32, i32, vp]
+        L.fizi_batch_relearn.argtypes = [vp, i32, vp, i32, vp, vp]
         L.fizi_batch_step.argtypes = [vp, P(vp), P(vp), vp, vp]
         L.fizi_batch_set_mode.argtypes = [vp, i32]
         L.fizi_batch_status.argtypes = [vp, P(ctypes.c_uint32)]
@@ -199,6 +201,20 @@ class Context:
         self._check_frames(frames)
         check(lib().learn_background(self._h, _ptr(frames), int(frames.shape[0]), int(bool(reset)),
                                      _stream(stream)))
+
+    def relearn_background(self, frames: torch.Tensor, fizi_bits: torch.Tensor, stream=None):
+        """Partial re-learning: widen the model with frames at the pixels
+        whose bit in fizi_bits ((n, H, W/64) int64, as process_frames
+        returns them) is 0."""
+        self._check_frames(frames)
+        self._check_bits(fizi_bits, int(frames.shape[0]))
+        check(lib().relearn_background(self._h, _ptr(frames), int(frames.shape[0]), _ptr(fizi_bits),
+                                       _stream(stream)))
+
+    def _check_bits(self, bits, n):
+        if (bits.dtype != torch.int64 or not bits.is_contiguous()
+                or tuple(bits.shape) != (n, self.height, self.width // 64)):
+            raise FiziError(FIZI_EINVAL, f"masks must be contiguous int64 ({n}, {self.height}, {self.width // 64})")
 
     def process_frames(self, frames: torch.Tensor, want_fizi=True, want_hand=False, stream=None):
         """Returns dict(pointers=(n,56) uint8, fizi=(n,H,W/64) int64 bits or
@@ -307,6 +323,17 @@ class Batch:
         check(lib().fizi_batch_learn(self._h, int(stream_id), _ptr(frames), int(frames.shape[0]),
                                      int(bool(reset)), _stream(stream)))
 
+    def relearn(self, stream_id, frames: torch.Tensor, fizi_bits: torch.Tensor, stream=None):
+        """Partial re-learning of one stream's model (see Context.relearn_background)."""
+        w, h = self.geoms[stream_id]
+        n = int(frames.shape[0])
+        if frames.dtype != torch.uint8 or not frames.is_contiguous() or tuple(frames.shape[1:]) != (h, w, 3):
+            raise FiziError(FIZI_EINVAL, f"frames must be contiguous uint8 (n, {h}, {w}, 3)")
+        if fizi_bits.dtype != torch.int64 or not fizi_bits.is_contiguous() or tuple(fizi_bits.shape) != (n, h, w // 64):
+            raise FiziError(FIZI_EINVAL, f"masks must be contiguous int64 ({n}, {h}, {w // 64})")
+        check(lib().fizi_batch_relearn(self._h, int(stream_id), _ptr(frames), n, _ptr(fizi_bits),
+                                       _stream(stream)))
+
     def step(self, frames, pointers: torch.Tensor, fizi=None, stream=None):
         """frames: list of n device frames (H, W, 3) uint8 or None (idle);
         pointers: (n, 56) uint8 device tensor; fizi: optional list of bit
@@ -389,6 +416,16 @@ def process_frames(ctx: Context, frames, want_fizi=True, want_hand=False, stream
 
 def get_pointer(ctx: Context, frame_index: int) -> dict:
     return ctx.get_pointer(frame_index)
+
+
+def pack_bits(mask, device=None) -> torch.Tensor:
+    """(..., H, W) 0/1 array (W a multiple of 64) -> (..., H, W/64) int64
+    LSB-first bit rows, the layout of I_FIZI masks."""
+    m = np.ascontiguousarray(np.asarray(mask) != 0)
+    b = np.packbits(m, axis=-1, bitorder="little")
+    words = np.ascontiguousarray(b).view(np.uint64).view(np.int64)
+    t = torch.from_numpy(words.copy())
+    return t.to(device) if device is not None else t
 
 
 def unpack_bits(words: torch.Tensor, width: int) -> np.ndarray:
