@@ -10,6 +10,8 @@
 namespace fizi {
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kSoftBlocksMax = 2048;
 constexpr int kSoftOut = 8;        // 6 gradients, loss, unused
 
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ fr
                         y4[u] |= (uint32_t)gt[4 * gi + k] << (8 * k);
                 }
             } else if (VEC) {
-                const float4 v = reinterpret_cast<const float4 *>(dLdm)[gi];
+                const f32x4 v = reinterpret_cast<const f32x4 *>(dLdm)[gi];
                 dm[u][0] = v.x;
                 dm[u][1] = v.y;
                 dm[u][2] = v.z;
