@@ -263,7 +263,7 @@ int fizi_batch_stage_times(fizi_batch *b, double *h_ms, int64_t *h_launches);
  * pixels (1, 2, 4, 8; not used by the persistent kernel, whose classify
  * work comes in bands of 4 * morph_rows rows); morph_rows: morphology band
  * height (8, 16, 32, 64); grid_per_cu: resident blocks per CU for the
- * streaming kernels (1..32); mode: FIZI_BATCH_*. Results do not depend on
+ * streaming kernels (1..64); mode: FIZI_BATCH_*. Results do not depend on
  * them. */
 typedef struct {
     int32_t cls_iters;

@@ -324,8 +324,8 @@ int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t)
         return fail(FIZI_EINVAL, "cls_iters must be 1, 2, 4 or 8");
     if (t->morph_rows != 8 && t->morph_rows != 16 && t->morph_rows != 32 && t->morph_rows != 64)
         return fail(FIZI_EINVAL, "morph_rows must be 8, 16, 32 or 64");
-    if (t->grid_per_cu < 1 || t->grid_per_cu > 32)
-        return fail(FIZI_EINVAL, "grid_per_cu must be in [1, 32]");
+    if (t->grid_per_cu < 1 || t->grid_per_cu > 64)
+        return fail(FIZI_EINVAL, "grid_per_cu must be in [1, 64]");
     if (t->mode < FIZI_BATCH_DIRECT || t->mode > FIZI_BATCH_PERSISTENT_GRAPH)
         return fail(FIZI_EINVAL, "unknown batch mode");
     if (b->have_last)
@@ -396,7 +396,7 @@ int fizi_batch_autotune(fizi_batch *b, const uint8_t *const *h_frames, fizi_poin
     if (rc == FIZI_OK)
         rc = sweep(&fizi_tuning::cls_iters, {2, 4, 8});
     if (rc == FIZI_OK)
-        rc = sweep(&fizi_tuning::grid_per_cu, {4, 8, 16});
+        rc = sweep(&fizi_tuning::grid_per_cu, {8, 16, 32, 64});
     if (rc == FIZI_OK)
         rc = sweep(&fizi_tuning::morph_rows, {8, 16, 32, 64});
     (void)hipEventDestroy(e0);
