@@ -34,7 +34,11 @@
  *   R8  the pointer = area, coordinate sums, bounding box and a fill-ratio
  *       click (Section 2 "its movement, its state (click or not)");
  *   R9  partial re-learning (Section 3.3) widens the model with running
- *       frames at the pixels their I_FIZI marks as background.
+ *       frames at the pixels their I_FIZI marks as background;
+ *   R10 temporal tracking (Section 2, the Mouse module "tracks" the hand):
+ *       when the previous frame had a hand, the component that covers its
+ *       centroid pixel (floor of the coordinate sums over the area) keeps the
+ *       hand if its area reaches min_area; otherwise R7 applies.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -369,8 +373,22 @@ int orc_label(const uint8_t *m, int W, int H, int32_t *labels)
 /* Pointer of a binary FIZI image: the largest component (ties: smallest first
  * raster index) gives area, coordinate sums and bounding box; the click is a
  * filled-box test. hand (nullable) receives the selected component. */
+/* The pointer of one I_FIZI mask. The hand zone is the component of largest
+ * area (ties: smallest first raster index) - unless (track_x, track_y) is a
+ * pixel (track_x >= 0) that lies in a component of area >= min_area: then
+ * that component (reading R10, temporal tracking: the zone that covers the
+ * previous frame's centroid keeps the hand). */
+int orc_pointer_track(const uint8_t *fizi, int W, int H, const orc_params *p, uint32_t inv,
+                      uint64_t frame_index, int32_t track_x, int32_t track_y, orc_pointer *out, uint8_t *hand);
+
 int orc_pointer_of(const uint8_t *fizi, int W, int H, const orc_params *p, uint32_t inv,
                    uint64_t frame_index, orc_pointer *out, uint8_t *hand)
+{
+    return orc_pointer_track(fizi, W, H, p, inv, frame_index, -1, -1, out, hand);
+}
+
+int orc_pointer_track(const uint8_t *fizi, int W, int H, const orc_params *p, uint32_t inv,
+                      uint64_t frame_index, int32_t track_x, int32_t track_y, orc_pointer *out, uint8_t *hand)
 {
     size_t npx = (size_t)W * H;
     int32_t *labels = (int32_t *)malloc(npx * sizeof(int32_t) + 4);
@@ -393,6 +411,11 @@ int orc_pointer_of(const uint8_t *fizi, int W, int H, const orc_params *p, uint3
     int best = 0;
     for (int l = 1; l <= K; l++) {
         if (best == 0 || area[l] > area[best] || (area[l] == area[best] && first[l] < first[best]))
+            best = l;
+    }
+    if (track_x >= 0 && track_x < W && track_y >= 0 && track_y < H) {
+        int32_t l = labels[(size_t)track_y * W + track_x];
+        if (l && area[l] >= (uint64_t)(p->min_area > 0 ? p->min_area : 0))
             best = l;
     }
     memset(out, 0, sizeof(*out));
@@ -437,9 +460,22 @@ int orc_pointer_of(const uint8_t *fizi, int W, int H, const orc_params *p, uint3
 /* One running-phase frame end to end: gain, correction, the three masks and
  * their AND, morphology, then the pointer. raw / fizi / hand are byte masks
  * (nullable except fizi). */
+int orc_process_track(const uint8_t *F, const uint8_t *bgmin, const uint8_t *bgmax,
+                      const uint16_t *yref, int W, int H, const orc_params *p, uint64_t frame_index,
+                      int32_t track_x, int32_t track_y, orc_pointer *out, uint8_t *raw_out, uint8_t *fizi,
+                      uint8_t *hand);
+
 int orc_process(const uint8_t *F, const uint8_t *bgmin, const uint8_t *bgmax,
                 const uint16_t *yref, int W, int H, const orc_params *p, uint64_t frame_index,
                 orc_pointer *out, uint8_t *raw_out, uint8_t *fizi, uint8_t *hand)
+{
+    return orc_process_track(F, bgmin, bgmax, yref, W, H, p, frame_index, -1, -1, out, raw_out, fizi, hand);
+}
+
+int orc_process_track(const uint8_t *F, const uint8_t *bgmin, const uint8_t *bgmax,
+                      const uint16_t *yref, int W, int H, const orc_params *p, uint64_t frame_index,
+                      int32_t track_x, int32_t track_y, orc_pointer *out, uint8_t *raw_out, uint8_t *fizi,
+                      uint8_t *hand)
 {
     size_t npx = (size_t)W * H;
     uint8_t *fc = (uint8_t *)malloc(npx * 3);
@@ -457,7 +493,7 @@ int orc_process(const uint8_t *F, const uint8_t *bgmin, const uint8_t *bgmax,
         memcpy(raw_out, raw, npx);
     rc = orc_morph(raw, W, H, p->open_iters, p->close_iters, fizi);
     if (rc == 0)
-        rc = orc_pointer_of(fizi, W, H, p, inv, frame_index, out, hand);
+        rc = orc_pointer_track(fizi, W, H, p, inv, frame_index, track_x, track_y, out, hand);
     free(fc);
     free(raw);
     return rc;

@@ -83,6 +83,11 @@ def lib():
                                      ctypes.c_uint64, P(Pointer), u8p]
         L.orc_process.argtypes = [u8p, u8p, u8p, P(ctypes.c_uint16), ctypes.c_int, ctypes.c_int,
                                   P(Params), ctypes.c_uint64, P(Pointer), u8p, u8p, u8p]
+        L.orc_process_track.argtypes = [u8p, u8p, u8p, P(ctypes.c_uint16), ctypes.c_int, ctypes.c_int,
+                                        P(Params), ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                        P(Pointer), u8p, u8p, u8p]
+        L.orc_pointer_track.argtypes = [u8p, ctypes.c_int, ctypes.c_int, P(Params), ctypes.c_uint32,
+                                        ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, P(Pointer), u8p]
         _lib = L
     return _lib
 
@@ -191,7 +196,9 @@ class Model:
             raise ValueError(f"orc_relearn failed ({rc})")
         return inv[:n]
 
-    def process(self, frame, frame_index=0, want_raw=False, want_hand=False):
+    def process(self, frame, frame_index=0, want_raw=False, want_hand=False, track=None):
+        """One running-phase frame. track: None (R7), or the previous frame's
+        centroid pixel (x, y) for temporal tracking (R10)."""
         f = _c(frame, np.uint8)
         npx = self.W * self.H
         fizi = np.zeros((self.H, self.W), np.uint8)
@@ -199,11 +206,12 @@ class Model:
         hand = np.zeros((self.H, self.W), np.uint8) if want_hand else None
         ptr = Pointer()
         null = ctypes.POINTER(ctypes.c_uint8)()
-        rc = lib().orc_process(_u8(f), _u8(self.bgmin), _u8(self.bgmax),
-                               self.yref.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
-                               self.W, self.H, ctypes.byref(self.p), int(frame_index),
-                               ctypes.byref(ptr), _u8(raw) if raw is not None else null,
-                               _u8(fizi), _u8(hand) if hand is not None else null)
+        tx, ty = track if track is not None else (-1, -1)
+        rc = lib().orc_process_track(_u8(f), _u8(self.bgmin), _u8(self.bgmax),
+                                     self.yref.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                     self.W, self.H, ctypes.byref(self.p), int(frame_index), int(tx), int(ty),
+                                     ctypes.byref(ptr), _u8(raw) if raw is not None else null,
+                                     _u8(fizi), _u8(hand) if hand is not None else null)
         if rc != 0:
             raise ValueError(f"orc_process failed ({rc})")
         assert fizi.size == npx
@@ -255,15 +263,39 @@ def label(m):
     return lab, int(k)
 
 
-def pointer_of(fizi, p=None, inv=65536, frame_index=0, want_hand=False):
+def centroid_pixel(ptr):
+    """The tracked pixel of a pointer (R10): floor of the coordinate sums over
+    the area, or None without a hand."""
+    if not ptr["present"]:
+        return None
+    return (ptr["sum_x"] // ptr["area"], ptr["sum_y"] // ptr["area"])
+
+
+class Tracker:
+    """Temporal tracking over a frame sequence (R10): each frame's hand is
+    the component that covers the previous frame's centroid pixel when it is
+    large enough, else the largest."""
+
+    def __init__(self, model):
+        self.m = model
+        self.prev = None
+
+    def process(self, frame, frame_index=0, want_hand=False):
+        out = self.m.process(frame, frame_index, want_hand=want_hand, track=self.prev)
+        self.prev = centroid_pixel(out["pointer"])
+        return out
+
+
+def pointer_of(fizi, p=None, inv=65536, frame_index=0, want_hand=False, track=None):
     p = p or params()
     m = _c(fizi, np.uint8)
     H, W = m.shape
     ptr = Pointer()
     hand = np.zeros((H, W), np.uint8) if want_hand else None
-    rc = lib().orc_pointer_of(_u8(m), W, H, ctypes.byref(p), int(inv), int(frame_index),
-                              ctypes.byref(ptr),
-                              _u8(hand) if hand is not None else ctypes.POINTER(ctypes.c_uint8)())
+    tx, ty = track if track is not None else (-1, -1)
+    rc = lib().orc_pointer_track(_u8(m), W, H, ctypes.byref(p), int(inv), int(frame_index), int(tx), int(ty),
+                                 ctypes.byref(ptr),
+                                 _u8(hand) if hand is not None else ctypes.POINTER(ctypes.c_uint8)())
     if rc != 0:
         raise MemoryError
     return (ptr.as_dict(), hand) if want_hand else ptr.as_dict()
