@@ -92,6 +92,21 @@ def bench_batched(args, torch, fizi, workloads):
         stream.synchronize()
         lat.append((time.perf_counter() - t) * 1e3)
 
+    # the same step with every stream tracked (temporal tracking, one frame
+    # per stream per step: the component stage stays parallel)
+    for i in range(n):
+        b.set_tracking(i, True)
+    for k in range(2):
+        b.step(workloads.step_frames(w, k), ptrs, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        b.step(workloads.step_frames(w, k), ptrs, stream=stream)
+    torch.cuda.synchronize()
+    track_sec = (time.perf_counter() - t0) / args.steps
+    for i in range(n):
+        b.set_tracking(i, False)
+
     # kernel durations from their own dispatch events: the same kernels and
     # grids, launched directly so that the events can be attached (the
     # persistent kernel reports its whole launch under "classify")
@@ -114,7 +129,7 @@ def bench_batched(args, torch, fizi, workloads):
         kernel, bpp = f"k_classify<{tuning['cls_iters']}> (I_R1, I_R2, I_R3 per pixel)", CLASSIFY_BYTES_PER_PX
     achieved = bpp * px / k_avg / 1e9
     return dict(w=w, px=px, n=n, sec=sec, lat=lat, k_avg=k_avg, achieved=achieved, kernel=kernel, bpp=bpp,
-                tuning=tuning, stages_us=stages_us)
+                tuning=tuning, stages_us=stages_us, track_sec=track_sec)
 
 
 def bench_plain(args, torch, fizi, scene):
@@ -138,6 +153,16 @@ def bench_plain(args, torch, fizi, scene):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
     fps = args.plain_batch / sec
+    # temporal tracking: the component stage of a call's frames runs in order
+    ctx.set_tracking(True)
+    ctx.process_into(pool, args.plain_batch, pointers=ptrs, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.process_into(pool, args.plain_batch, pointers=ptrs, stream=stream)
+    torch.cuda.synchronize()
+    track_fps = args.plain_batch * reps / (time.perf_counter() - t0)
+    ctx.set_tracking(False)
     ctx1 = fizi.Context(W, H, chunk=1, device=dev)
     ctx1.learn_background(bg)
     one = torch.empty((1, 56), dtype=torch.uint8, device=dev)
@@ -152,6 +177,7 @@ def bench_plain(args, torch, fizi, scene):
     return {"workload": "one 1920x1080 stream, frames processed in batches of "
                         f"{args.plain_batch} (internal launches of {scene.HD_CHUNK} frames)",
             "Mpixel_per_s": round(fps * W * H / 1e6, 1), "frames_per_s": round(fps, 1),
+            "tracking_frames_per_s": round(track_fps, 1),
             "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99),
                            "mode": "one frame per call, pointer read back on the host"}}
 
@@ -365,6 +391,7 @@ def main():
                      "avg_launch_us": round(r["k_avg"] * 1e6, 2),
                      "bytes_per_launch": int(r["bpp"] * r["px"])},
         "stage_us": r["stages_us"],
+        "tracking_ms_per_step": round(r["track_sec"] * 1e3, 4),
         "plain_single_stream": plain,
         "serving": serving,
         "soft_mask": soft_res,

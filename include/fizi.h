@@ -179,6 +179,15 @@ int process_frames(fizi_ctx *ctx, const uint8_t *d_frames, int32_t n_frames,
                    uint64_t *d_fizi_bits, uint64_t *d_hand_bits, fizi_pointer *d_pointers,
                    void *stream);
 
+/* Temporal tracking of the hand (the Mouse module "tracks" the hand zone,
+ * Section 2): with enable != 0, when the previous frame had a hand, the
+ * component that covers its centroid pixel (floor of the coordinate sums over
+ * the area) keeps the hand if its area reaches min_area; otherwise the
+ * largest component is taken, as without tracking. Frames of a call are
+ * tracked in order (their component stage then runs one frame after the
+ * other). Waits for the context's work and clears the tracking state. */
+int fizi_set_tracking(fizi_ctx *ctx, int32_t enable);
+
 /* Waits for the frame with running index frame_index and copies its pointer
  * to *h_out. The last 65536 frames are kept; older or not yet submitted
  * indices give FIZI_ERANGE. */
@@ -229,6 +238,10 @@ int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_para
 /* learn_background for one stream of the batch. Async. */
 int fizi_batch_learn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, int32_t n_frames,
                      int32_t reset, void *stream);
+
+/* fizi_set_tracking for stream stream_id of the batch (one frame per step,
+ * so tracked streams keep the batch's parallel component stage). */
+int fizi_batch_set_tracking(fizi_batch *b, int32_t stream_id, int32_t enable);
 
 /* relearn_background for stream stream_id of the batch. */
 int fizi_batch_relearn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, int32_t n_frames,

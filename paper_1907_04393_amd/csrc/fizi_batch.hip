@@ -239,6 +239,21 @@ int fizi_batch_relearn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames
     return mark_last(b, s);
 }
 
+int fizi_batch_set_tracking(fizi_batch *b, int32_t stream_id, int32_t enable)
+{
+    if (!b)
+        return fail(FIZI_EINVAL, "null batch");
+    if (stream_id < 0 || stream_id >= b->n)
+        return fail(FIZI_EINVAL, "stream_id out of range");
+    if (b->have_last)
+        FIZI_HIP(hipEventSynchronize(b->order_ev));
+    Model &m = b->m[stream_id];
+    FIZI_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(m.track), 0u, sizeof(TrackState) / 4, nullptr));
+    FIZI_HIP(hipStreamSynchronize(nullptr));
+    m.tracking = enable != 0;
+    return FIZI_OK;
+}
+
 int fizi_batch_set_mode(fizi_batch *b, int32_t mode)
 {
     if (!b)

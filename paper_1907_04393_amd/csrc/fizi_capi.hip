@@ -316,6 +316,18 @@ int fizi_stage_times(fizi_ctx *c, double *h_ms, int64_t *h_launches)
     return c->clk.read(h_ms, h_launches);
 }
 
+int fizi_set_tracking(fizi_ctx *c, int32_t enable)
+{
+    if (!c)
+        return fail(FIZI_EINVAL, "null context");
+    if (c->have_last)
+        FIZI_HIP(hipEventSynchronize(c->order_ev));
+    FIZI_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(c->m.track), 0u, sizeof(TrackState) / 4, nullptr));
+    FIZI_HIP(hipStreamSynchronize(nullptr));
+    c->m.tracking = enable != 0;
+    return FIZI_OK;
+}
+
 int fizi_destroy(fizi_ctx *c)
 {
     if (!c)

@@ -50,7 +50,9 @@ struct Model {
     uint8_t *bgmax = nullptr;
     uint16_t *yref = nullptr;
     int yref_rows = 0;
+    TrackState *track = nullptr;       // device memory, after the reference luminance
     bool learned = false;
+    bool tracking = false;
 };
 size_t model_bytes(const fizi_geom &g, const fizi_params &p);
 void model_at(Model &m, const fizi_geom &g, const fizi_params &p, uint8_t *base);

@@ -116,7 +116,7 @@ size_t model_bytes(const fizi_geom &g, const fizi_params &p)
 {
     const size_t px = (size_t)g.width * g.height;
     const size_t rows = (g.height + p.gain_row_stride - 1) / p.gain_row_stride;
-    return 2 * align256(px * 3) + align256(rows * g.width * 2);
+    return 2 * align256(px * 3) + align256(rows * g.width * 2) + align256(sizeof(TrackState));
 }
 
 void model_at(Model &m, const fizi_geom &g, const fizi_params &p, uint8_t *base)
@@ -129,7 +129,10 @@ void model_at(Model &m, const fizi_geom &g, const fizi_params &p, uint8_t *base)
     m.bgmin = base;
     m.bgmax = base + align256(px * 3);
     m.yref = reinterpret_cast<uint16_t *>(base + 2 * align256(px * 3));
+    m.track = reinterpret_cast<TrackState *>(base + 2 * align256(px * 3) +
+                                             align256((size_t)m.yref_rows * g.width * 2));
     m.learned = false;
+    m.tracking = false;
 }
 
 size_t slot_bytes(const fizi_geom &g)
@@ -185,6 +188,7 @@ void fill_job(const Model &m, int band, Job &J)
     J.glo = m.p.gain_lo_q16;
     J.ghi = m.p.gain_hi_q16;
     J.hue = m.hue;
+    J.track = m.tracking ? m.track : nullptr;
 }
 
 void set_scratch(Job &J, const Slot &s)
@@ -380,7 +384,9 @@ int run_pipeline(const Table *d_tab, const Table &h, int njobs, int max_jobs, in
                              ev(FIZI_STAGE_CLASSIFY)));
     FIZI_HIP(launch_morph(d_tab, fixed_grid ? big : h.h.mor_pre[njobs], max_wd, max_ops, n_cu, t, s,
                           ev(FIZI_STAGE_MORPH)));
-    FIZI_HIP(launch_resolve(d_tab, fixed_grid ? max_jobs : njobs, s, ev(FIZI_STAGE_RESOLVE)));
+    // tracked consecutive frames of one stream are resolved in order
+    const bool serial = njobs > 1 && h.jobs[0].track != nullptr && h.jobs[1].track == h.jobs[0].track;
+    FIZI_HIP(launch_resolve(d_tab, fixed_grid ? max_jobs : njobs, s, ev(FIZI_STAGE_RESOLVE), serial));
     return FIZI_OK;
 }
 

@@ -46,6 +46,12 @@ struct HueTest {
     int32_t pad;
 };
 
+// Temporal tracking state of one stream (device memory): the previous
+// frame's centroid pixel, valid when that frame had a hand.
+struct TrackState {
+    int32_t valid, x, y, pad;
+};
+
 struct Job {
     const uint8_t *frame;      // H*W*3
     const uint8_t *bgmin;      // H*W*3
@@ -60,6 +66,7 @@ struct Job {
     uint2 *runs;               // run_cap runs (first pixel, last pixel | link flag)
     uint2 *links;              // link_cap pairs of run starts to join
     fizi_pointer *out;         // one pointer
+    TrackState *track;         // the stream's tracking state, or null (largest component)
     uint64_t frame_index;
     int32_t W, H, Wd, rs;
     uint32_t run_cap, link_cap;
@@ -136,7 +143,9 @@ hipError_t launch_classify(const Table *d_tab, int total_tiles, int n_cu, const 
                            hipStream_t s, StageEvents ev = {});
 hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max_ops, int n_cu,
                         const Tuning &t, hipStream_t s, StageEvents ev = {});
-hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev = {});
+// serial: one workgroup takes the jobs in table order (consecutive frames of
+// one tracked stream).
+hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev = {}, bool serial = false);
 hipError_t launch_persistent(const Table *d_tab, int max_wd, int max_ops, int n_cu, const Tuning &t,
                              uint8_t *persist, hipStream_t s, StageEvents ev = {});
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);

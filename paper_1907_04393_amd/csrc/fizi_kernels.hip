@@ -1326,8 +1326,31 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
     }
     best = block_reduce<unsigned long long>(best, s_u64, OpMax());
     ncomp = block_reduce<uint32_t>(ncomp, s_u32, OpAdd());
-    const uint32_t A = (uint32_t)(best >> 32);
-    const uint32_t kstar = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
+    // temporal tracking: the component that covers the previous frame's
+    // centroid pixel keeps the hand when its area reaches min_area
+    __shared__ uint32_t s_pick;
+    if (threadIdx.x == 0) {
+        uint32_t pick = 0xFFFFFFFFu;
+        const TrackState *ts = J->track;
+        if (ts && ts->valid) {
+            const int tx = ts->x, ty = ts->y;
+            if (tx >= 0 && tx < W && ty >= 0 && ty < H) {
+                const GLOBAL uint64_t *row = fz + (size_t)ty * Wd;
+                if ((row[tx >> 6] >> (tx & 63)) & 1ull) {
+                    const uint32_t start = (uint32_t)ty * (uint32_t)W + (uint32_t)(prev_zero(row, tx) + 1);
+                    const uint32_t r = find_root(parent, start);
+                    if ((long long)ld_wg(area + r) >= (long long)max(J->min_area, 0))
+                        pick = r;
+                }
+            }
+        }
+        s_pick = pick;
+    }
+    __syncthreads();
+    const uint32_t pick = s_pick;
+    const bool tracked = pick != 0xFFFFFFFFu;
+    const uint32_t A = tracked ? ld_wg(area + pick) : (uint32_t)(best >> 32);
+    const uint32_t kstar = tracked ? pick : 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
     const bool present = ncomp > 0 && (long long)A >= (long long)J->min_area;
     // D: sums and box of the selected component
     unsigned long long sx = 0, sy = 0;
@@ -1386,6 +1409,14 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
         o.inv_gain_q16 = inv;
         o.frame_index = J->frame_index;
         *J->out = o;
+        if (J->track) {
+            TrackState *ts = J->track;
+            ts->valid = present ? 1 : 0;
+            if (present) {
+                ts->x = (int32_t)(sx / A);
+                ts->y = (int32_t)(sy / A);
+            }
+        }
     }
     __syncthreads();
 }
@@ -1620,11 +1651,11 @@ hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev)
+hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev, bool serial)
 {
     if (njobs <= 0)
         return hipSuccess;
-    FIZI_LAUNCH(k_resolve, njobs, kResolveThreads, 0, s, ev, const_cast<Table *>(d_tab));
+    FIZI_LAUNCH(k_resolve, serial ? 1 : njobs, kResolveThreads, 0, s, ev, const_cast<Table *>(d_tab));
     return hipGetLastError();
 }
 

@@ -89,6 +89,7 @@ def lib():
     L.fizi_create.argtypes = [P(Geom), P(Params), i32, vp, ctypes.c_size_t, vp, P(vp)]
     L.learn_background.argtypes = [vp, vp, i32, i32, vp]
     L.relearn_background.argtypes = [vp, vp, i32, vp, vp]
+    L.fizi_set_tracking.argtypes = [vp, i32]
     L.process_frames.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     L.get_pointer.argtypes = [vp, i64, P(PointerC)]
     L.fizi_destroy.argtypes = [vp]
@@ -108,6 +109,7 @@ def _extra_signatures(L):
         L.fizi_batch_create.argtypes = [i32, P(Geom), P(Params), vp, ctypes.c_size_t, P(vp)]
         L.fizi_batch_learn.argtypes = [vp, i32, vp, i32, i32, vp]
         L.fizi_batch_relearn.argtypes = [vp, i32, vp, i32, vp, vp]
+        L.fizi_batch_set_tracking.argtypes = [vp, i32, i32]
         L.fizi_batch_step.argtypes = [vp, P(vp), P(vp), vp, vp]
         L.fizi_batch_set_mode.argtypes = [vp, i32]
         L.fizi_batch_status.argtypes = [vp, P(ctypes.c_uint32)]
@@ -210,6 +212,10 @@ class Context:
         self._check_bits(fizi_bits, int(frames.shape[0]))
         check(lib().relearn_background(self._h, _ptr(frames), int(frames.shape[0]), _ptr(fizi_bits),
                                        _stream(stream)))
+
+    def set_tracking(self, enable=True):
+        """Temporal tracking of the hand zone (see fizi_set_tracking)."""
+        check(lib().fizi_set_tracking(self._h, int(bool(enable))))
 
     def _check_bits(self, bits, n):
         if (bits.dtype != torch.int64 or not bits.is_contiguous()
@@ -322,6 +328,9 @@ class Batch:
             raise FiziError(FIZI_EINVAL, f"frames must be contiguous uint8 (n, {h}, {w}, 3)")
         check(lib().fizi_batch_learn(self._h, int(stream_id), _ptr(frames), int(frames.shape[0]),
                                      int(bool(reset)), _stream(stream)))
+
+    def set_tracking(self, stream_id, enable=True):
+        check(lib().fizi_batch_set_tracking(self._h, int(stream_id), int(bool(enable))))
 
     def relearn(self, stream_id, frames: torch.Tensor, fizi_bits: torch.Tensor, stream=None):
         """Partial re-learning of one stream's model (see Context.relearn_background)."""

@@ -1,0 +1,143 @@
+"""GPU parity of temporal tracking (reading R10) with the oracle's Tracker:
+plain contexts (frames of a call tracked in order, in chunks), the batched
+form in every launch mode, and the reset on enabling."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+W, H = 128, 64
+BIG = (10, 10, 49, 39)
+
+
+def _rect(m, x0, y0, x1, y1):
+    m[y0:y1 + 1, x0:x1 + 1] = 1
+
+
+def _sequence():
+    """Frames 0-1: a small square alone; 2-5: a big static rectangle joins
+    while the square moves on; 6: the square is gone; 7-8: it is back."""
+    masks = []
+    for k in range(9):
+        m = np.zeros((H, W), np.uint8)
+        if k >= 2:
+            _rect(m, *BIG)
+        if k != 6:
+            x0 = 60 + 3 * k
+            _rect(m, x0, 20, x0 + 9, 29)
+        masks.append(m)
+    masks = np.stack(masks)
+    bg = np.zeros((2, H, W, 3), np.uint8)
+    bg[...] = (40, 40, 90)
+    fr = np.repeat(bg[:1], len(masks), axis=0).copy()
+    fr[masks.astype(bool)] = (210, 140, 90)
+    return torch.from_numpy(bg), torch.from_numpy(fr), masks
+
+
+PARAMS = dict(open_iters=0, close_iters=0)
+
+
+def _oracle_track(bg, fr, params, prev=None):
+    from oracle import oracle
+    m = oracle.Model(bg.shape[2], bg.shape[1], oracle.params(**params))
+    m.learn(bg.numpy())
+    t = oracle.Tracker(m)
+    t.prev = prev
+    return [t.process(fr[k].numpy(), frame_index=k, want_hand=True) for k in range(fr.shape[0])]
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 8])
+def test_plain_tracking_matches_oracle(chunk):
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    bg, fr, masks = _sequence()
+    ref = _oracle_track(bg, fr, PARAMS)
+    # the tracker really departs from the largest component here
+    assert ref[3]["pointer"]["area"] == 100 and ref[7]["pointer"]["area"] == 1200
+    ctx = fizi.Context(W, H, fizi.default_params(**PARAMS), chunk=chunk, device=dev)
+    ctx.learn_background(bg.to(dev))
+    ctx.set_tracking(True)
+    out = ctx.process_frames(fr.to(dev), want_fizi=True, want_hand=True)
+    torch.cuda.synchronize()
+    got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(out["pointers"])]
+    hand = fizi.unpack_bits(out["hand"], W)
+    for k in range(fr.shape[0]):
+        assert got[k] == ref[k]["pointer"], (chunk, k, got[k], ref[k]["pointer"])
+        assert np.array_equal(hand[k], ref[k]["hand"]), (chunk, k)
+
+
+def test_tracking_across_calls_and_reset():
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    bg, fr, _ = _sequence()
+    ref = _oracle_track(bg, fr, PARAMS)
+    ctx = fizi.Context(W, H, fizi.default_params(**PARAMS), chunk=2, device=dev)
+    ctx.learn_background(bg.to(dev))
+    ctx.set_tracking(True)
+    got = []
+    for k in range(5):                          # one frame per call
+        out = ctx.process_frames(fr[k:k + 1].to(dev))
+        torch.cuda.synchronize()
+        got.append(fizi.pointer_dict(fizi.pointers_to_numpy(out["pointers"])[0]))
+    for k in range(5):
+        g = dict(got[k]); g["frame_index"] = k
+        assert g == ref[k]["pointer"], k
+    # enabling again forgets the previous hand: frame 5 then takes the largest
+    ctx.set_tracking(True)
+    out = ctx.process_frames(fr[5:6].to(dev))
+    torch.cuda.synchronize()
+    p = fizi.pointer_dict(fizi.pointers_to_numpy(out["pointers"])[0])
+    assert p["area"] == 1200
+    ctx.set_tracking(False)
+
+
+def test_scene_tracking_matches_oracle():
+    """A generated scene with two static skin distractors, 40 frames in
+    chunks of 16."""
+    from paper_1907_04393_amd import fizi, scene
+    dev = need_gpu()
+    sp = scene.SceneSpec(320, 240, sigma=3, seed=(9, 2, 0, 0), distractors=2)
+    sc = scene.Scene(sp)
+    bg, hand = sc.bg_frames(0, 20), sc.hand_frames(0, 40)
+    ref = _oracle_track(bg, hand, {})
+    ctx = fizi.Context(320, 240, chunk=16, device=dev)
+    ctx.learn_background(bg.to(dev))
+    ctx.set_tracking(True)
+    out = ctx.process_frames(hand.to(dev), want_hand=True)
+    torch.cuda.synchronize()
+    got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(out["pointers"])]
+    hd = fizi.unpack_bits(out["hand"], 320)
+    for k in range(40):
+        assert got[k] == ref[k]["pointer"], k
+        assert np.array_equal(hd[k], ref[k]["hand"]), k
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_batch_tracking_matches_oracle(mode):
+    from oracle import oracle
+    from paper_1907_04393_amd import fizi
+    from test_gpu_plain import _blob_scene
+    dev = need_gpu()
+    bg, fr, _ = _sequence()
+    bgb, frb = _blob_scene(192, 70, 4, 9, seed=21)
+    b = fizi.Batch([(W, H), (192, 70)], [fizi.default_params(**PARAMS), fizi.default_params()], device=dev)
+    b.set_mode(mode)
+    b.learn(0, bg.to(dev))
+    b.learn(1, bgb.to(dev))
+    b.set_tracking(0, True)
+    ref_a = _oracle_track(bg, fr, PARAMS)
+    mb = oracle.Model(192, 70)
+    mb.learn(bgb.numpy())
+    fa, fb = fr.to(dev), frb.to(dev)
+    for k in range(fr.shape[0]):
+        ptrs = torch.empty((2, 56), dtype=torch.uint8, device=dev)
+        b.step([fa[k], fb[k]], ptrs)
+        torch.cuda.synchronize()
+        got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(ptrs)]
+        assert got[0] == ref_a[k]["pointer"], (mode, k)
+        assert got[1] == mb.process(frb[k].numpy(), frame_index=k)["pointer"], (mode, k)
+    assert b.status() == 0
+    b.close()
