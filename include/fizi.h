@@ -335,6 +335,44 @@ int fizi_soft_backward(const uint8_t *d_frames, const float *d_dLdm, int64_t npx
 int fizi_soft_bce(const uint8_t *d_frames, const uint8_t *d_gt, int64_t npx, const float params6[6],
                   float T, void *d_workspace, size_t workspace_bytes, double *d_out7, void *stream);
 
+/* ---- The pointer's consumers (host) ---------------------------------------
+ * A pointer's position is its centroid pixel (floor(sum_x / area),
+ * floor(sum_y / area)); a frame without a hand has none. */
+
+/* An inclusive rectangle of image pixels. */
+typedef struct {
+    int32_t x0, y0, x1, y1;
+} fizi_zone;
+
+/* Interface module (Section 2: "the interface zone activated by the
+ * pointer"): h_zone[i] = the first zone, in array order, that holds pointer
+ * i's position, or -1 (no hand, or no zone holds it). Host arrays;
+ * synchronous. */
+int fizi_zone_hit(const fizi_pointer *h_pointers, int32_t n, const fizi_zone *h_zones, int32_t n_zones,
+                  int32_t *h_zone);
+
+/* A virtual wheel centred at (cx, cy): positions at a distance in
+ * [r_min, r_max] are on it; no steering within +-dead_cdeg of 12 o'clock,
+ * full lock at +-full_cdeg (0 <= dead_cdeg < full_cdeg <= 18000). */
+typedef struct {
+    int32_t cx, cy, r_min, r_max;
+    int32_t dead_cdeg, full_cdeg;
+} fizi_wheel;
+
+typedef struct {
+    int32_t on_wheel;          /* 1 when the position lies on the wheel */
+    int32_t angle_cdeg;        /* from 12 o'clock, clockwise > 0, in (-18000, 18000],
+                                  rounded half away from zero */
+    int32_t steer_permille;    /* 0 in the dead zone, then linear to +-1000 at full lock;
+                                  < 0 is left */
+    int32_t accelerate;        /* the pointer's click (closed palm) */
+} fizi_drive;
+
+/* Driving application (Section 4: the hand turns an imaginary wheel that
+ * controls left, right and speed): one fizi_drive per pointer (all zero off
+ * the wheel or without a hand). Host arrays; synchronous. */
+int fizi_drive_of(const fizi_pointer *h_pointers, int32_t n, const fizi_wheel *wheel, fizi_drive *h_out);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *fizi_last_error(void);
 

@@ -62,6 +62,17 @@ POINTER_DTYPE = np.dtype([("present", "u1"), ("click", "u1"), ("reserved", "<u2"
 assert POINTER_DTYPE.itemsize == ctypes.sizeof(PointerC) == 56
 
 
+class ZoneC(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("x0", "y0", "x1", "y1")]
+
+
+class WheelC(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("cx", "cy", "r_min", "r_max", "dead_cdeg", "full_cdeg")]
+
+
+DRIVE_FIELDS = ("on_wheel", "angle_cdeg", "steer_permille", "accelerate")
+
+
 class FiziError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"fizi error {code}: {msg}")
@@ -96,6 +107,9 @@ def lib():
     L.fizi_stage_timing.argtypes = [vp, i32]
     L.fizi_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
     _extra_signatures(L)
+    if hasattr(L, "fizi_zone_hit"):
+        L.fizi_zone_hit.argtypes = [vp, i32, vp, i32, vp]
+        L.fizi_drive_of.argtypes = [vp, i32, P(WheelC), vp]
     _lib = L
     return L
 
@@ -425,6 +439,38 @@ def process_frames(ctx: Context, frames, want_fizi=True, want_hand=False, stream
 
 def get_pointer(ctx: Context, frame_index: int) -> dict:
     return ctx.get_pointer(frame_index)
+
+
+def _host_pointers(pointers) -> np.ndarray:
+    """fizi_pointer records as a contiguous host array: a structured array of
+    POINTER_DTYPE, or an (n, 56) uint8 tensor (device or host)."""
+    if isinstance(pointers, torch.Tensor):
+        pointers = pointers_to_numpy(pointers)
+    a = np.ascontiguousarray(pointers)
+    if a.dtype != POINTER_DTYPE:
+        raise TypeError("pointers must have the fizi_pointer layout")
+    return a.reshape(-1)
+
+
+def zone_hit(pointers, zones) -> np.ndarray:
+    """Index of the first zone (x0, y0, x1, y1), inclusive, that holds each
+    pointer's centroid pixel, or -1 (the Interface module, Section 2)."""
+    p = _host_pointers(pointers)
+    z = np.ascontiguousarray(np.asarray(zones, dtype=np.int32).reshape(-1, 4))
+    out = np.empty(len(p), dtype=np.int32)
+    check(lib().fizi_zone_hit(p.ctypes.data, len(p), z.ctypes.data, len(z), out.ctypes.data))
+    return out
+
+
+def drive_of(pointers, wheel) -> np.ndarray:
+    """Virtual-wheel driving (Section 4) for each pointer; wheel =
+    (cx, cy, r_min, r_max, dead_cdeg, full_cdeg). Returns an (n, 4) int32
+    array with columns DRIVE_FIELDS."""
+    p = _host_pointers(pointers)
+    out = np.empty((len(p), 4), dtype=np.int32)
+    w = WheelC(*[int(v) for v in wheel])
+    check(lib().fizi_drive_of(p.ctypes.data, len(p), ctypes.byref(w), out.ctypes.data))
+    return out
 
 
 def pack_bits(mask, device=None) -> torch.Tensor:
