@@ -43,7 +43,7 @@ LAUNCH_NAMES = {0: "four kernels, direct launches", 1: "four kernels replayed fr
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB -> 1 GiB
 # elementwise kernel gives), keyed by kernel; valid only for the kernel code
 # the counters were taken on
-TRAFFIC = {"k_classify<4> (I_R1, I_R2, I_R3 per pixel)": 1714.0e6}
+TRAFFIC = {"k_classify<4> (I_R1, I_R2, I_R3 per pixel)": 1714.1e6}
 
 
 def log(*a):

@@ -92,6 +92,14 @@ typedef struct {
     int32_t gain_row_stride;   /* 1..64 */
     int32_t gain_lo_q16;       /* 1..2^20 */
     int32_t gain_hi_q16;       /* gain_lo_q16..2^20 */
+    /* Section 3.2 names two ways to follow the brightness: correct the
+     * pixels (0, the default, as above) or adapt the thresholds (1): the
+     * pixels stay raw, and with the frame's gain g = 2^16 / inv a channel v
+     * is inside the box when (bgmin - delta) g <= v <= (bgmax + delta) g and
+     * the pixel is gray when max - min < S g (compared exactly, as v * inv
+     * against bound * 2^16); the hue is the raw pixel's. The gain itself and
+     * the learning (on corrected frames) do not change. */
+    int32_t brightness_mode;   /* 0 or 1 */
 } fizi_params;
 
 /* One frame's pointer (56 bytes). When `present` is 0 every field except

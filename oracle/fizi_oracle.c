@@ -38,7 +38,12 @@
  *   R10 temporal tracking (Section 2, the Mouse module "tracks" the hand):
  *       when the previous frame had a hand, the component that covers its
  *       centroid pixel (floor of the coordinate sums over the area) keeps the
- *       hand if its area reaches min_area; otherwise R7 applies.
+ *       hand if its area reaches min_area; otherwise R7 applies;
+ *   R12 adaptive thresholds (Section 3.2, "adaptive threshold or modify the
+ *       dependent values consequently"): with brightness_mode 1 the pixels
+ *       stay raw and the thresholds of I_R1 and I_R2 are brought to the
+ *       frame's brightness instead (multiplied by the gain 2^16 / inv);
+ *       the hue is the raw pixel's.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -56,6 +61,7 @@ typedef struct {
     int32_t gain_row_stride;      /* rows sampled for the gain */
     int32_t gain_lo_q16;          /* clamp of the inverse gain, Q16 */
     int32_t gain_hi_q16;
+    int32_t brightness_mode;      /* 0: correct the pixels, 1: scale the thresholds */
 } orc_params;
 
 typedef struct {
@@ -265,6 +271,38 @@ void orc_masks(const uint8_t *Fc, const uint8_t *bgmin, const uint8_t *bgmax, si
         int mx = imax(v[0], imax(v[1], v[2]));
         int mn = imin(v[0], imin(v[1], v[2]));
         int notgray = (mx - mn) >= p->gray_S;
+        int skin = orc_hue_in(v[0], v[1], v[2], p->alpha1_cdeg, p->alpha2_cdeg);
+        if (r1) r1[i] = (uint8_t)out;
+        if (r2) r2[i] = (uint8_t)notgray;
+        if (r3) r3[i] = (uint8_t)skin;
+        if (raw) raw[i] = (uint8_t)(out && notgray && skin);
+    }
+}
+
+/* ---- Section 3.2, the other option: adaptive thresholds (reading R12) -----
+ * The frame F stays raw. With the frame's gain g = 2^16 / inv (the factor
+ * that maps the reference brightness to this frame's), channel v is inside
+ * the learned box when (bgmin - delta) g <= v <= (bgmax + delta) g, and the
+ * pixel is gray when max - min < S g. Both are compared exactly, as
+ * v inv against bound 2^16. I_R3 is the hue of the raw pixel. */
+void orc_masks_scaled(const uint8_t *F, const uint8_t *bgmin, const uint8_t *bgmax, size_t npx,
+                      uint32_t inv, const orc_params *p, uint8_t *r1, uint8_t *r2, uint8_t *r3,
+                      uint8_t *raw)
+{
+    const int64_t one = 65536;
+    for (size_t i = 0; i < npx; i++) {
+        const uint8_t *v = F + i * 3;
+        int out = 0;
+        for (int c = 0; c < 3; c++) {
+            int64_t scaled = (int64_t)v[c] * inv;
+            int64_t lo = ((int64_t)bgmin[i * 3 + c] - p->bg_delta) * one;
+            int64_t hi = ((int64_t)bgmax[i * 3 + c] + p->bg_delta) * one;
+            if (scaled < lo || scaled > hi)
+                out = 1;
+        }
+        int mx = imax(v[0], imax(v[1], v[2]));
+        int mn = imin(v[0], imin(v[1], v[2]));
+        int notgray = (int64_t)(mx - mn) * inv >= (int64_t)p->gray_S * one;
         int skin = orc_hue_in(v[0], v[1], v[2], p->alpha1_cdeg, p->alpha2_cdeg);
         if (r1) r1[i] = (uint8_t)out;
         if (r2) r2[i] = (uint8_t)notgray;
@@ -487,8 +525,12 @@ int orc_process_track(const uint8_t *F, const uint8_t *bgmin, const uint8_t *bgm
         return -2;
     }
     uint32_t inv = orc_gain(F, yref, W, H, p);
-    orc_correct(F, inv, npx * 3, fc);
-    orc_masks(fc, bgmin, bgmax, npx, p, NULL, NULL, NULL, raw);
+    if (p->brightness_mode == 1) {
+        orc_masks_scaled(F, bgmin, bgmax, npx, inv, p, NULL, NULL, NULL, raw);
+    } else {
+        orc_correct(F, inv, npx * 3, fc);
+        orc_masks(fc, bgmin, bgmax, npx, p, NULL, NULL, NULL, raw);
+    }
     if (raw_out)
         memcpy(raw_out, raw, npx);
     rc = orc_morph(raw, W, H, p->open_iters, p->close_iters, fizi);

@@ -22,7 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # Defaults of the readings (hue interval, margins, morphology, click, gain).
 DEFAULTS = dict(alpha1_cdeg=33000, alpha2_cdeg=7500, gray_S=20, bg_delta=10,
                 open_iters=1, close_iters=1, min_area=1, click_fill_permille=700,
-                gain_row_stride=8, gain_lo_q16=32768, gain_hi_q16=131072)
+                gain_row_stride=8, gain_lo_q16=32768, gain_hi_q16=131072, brightness_mode=0)
 
 
 class Params(ctypes.Structure):
@@ -75,6 +75,8 @@ def lib():
         L.orc_relearn.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(Params), u8p, u8p,
                                   P(ctypes.c_uint16), P(ctypes.c_uint32)]
         L.orc_masks.argtypes = [u8p, u8p, u8p, ctypes.c_size_t, P(Params), u8p, u8p, u8p, u8p]
+        L.orc_masks_scaled.argtypes = [u8p, u8p, u8p, ctypes.c_size_t, ctypes.c_uint32, P(Params),
+                                       u8p, u8p, u8p, u8p]
         L.orc_erode.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int]
         L.orc_dilate.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int]
         L.orc_morph.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p]
@@ -230,6 +232,18 @@ def masks(frame_corrected, bgmin, bgmax, p=None):
     outs = [np.zeros((H, W), np.uint8) for _ in range(4)]
     lib().orc_masks(_u8(f), _u8(_c(bgmin, np.uint8)), _u8(_c(bgmax, np.uint8)), H * W,
                     ctypes.byref(p), *[_u8(o) for o in outs])
+    return dict(r1=outs[0], r2=outs[1], r3=outs[2], raw=outs[3])
+
+
+def masks_scaled(frame_raw, inv, bgmin, bgmax, p=None):
+    """The three masks with the thresholds scaled to the frame's brightness
+    (reading R12) instead of corrected pixels."""
+    p = p or params()
+    f = _c(frame_raw, np.uint8)
+    H, W = f.shape[:2]
+    outs = [np.zeros((H, W), np.uint8) for _ in range(4)]
+    lib().orc_masks_scaled(_u8(f), _u8(_c(bgmin, np.uint8)), _u8(_c(bgmax, np.uint8)), H * W, int(inv),
+                           ctypes.byref(p), *[_u8(o) for o in outs])
     return dict(r1=outs[0], r2=outs[1], r3=outs[2], raw=outs[3])
 
 

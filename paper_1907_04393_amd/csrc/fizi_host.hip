@@ -92,6 +92,8 @@ int validate(const fizi_geom *g, const fizi_params *p)
         return fail(FIZI_EINVAL, "gain_row_stride must be in [1, 64]");
     if (p->gain_lo_q16 < 1 || p->gain_hi_q16 < p->gain_lo_q16 || p->gain_hi_q16 > (1 << 20))
         return fail(FIZI_EINVAL, "need 1 <= gain_lo_q16 <= gain_hi_q16 <= 2^20");
+    if (p->brightness_mode != 0 && p->brightness_mode != 1)
+        return fail(FIZI_EINVAL, "brightness_mode must be 0 or 1");
     return FIZI_OK;
 }
 
@@ -187,6 +189,8 @@ void fill_job(const Model &m, int band, Job &J)
     J.fill_pm = m.p.click_fill_permille;
     J.glo = m.p.gain_lo_q16;
     J.ghi = m.p.gain_hi_q16;
+    J.scaled = m.p.brightness_mode;
+    J.S_q16 = std::max((uint32_t)m.p.gray_S << 16, 1u);
     J.hue = m.hue;
     J.track = m.tracking ? m.track : nullptr;
 }

@@ -73,6 +73,8 @@ struct Job {
     uint32_t epoch;            // this dispatch's number for its scratch slot (never 0)
     int32_t band;              // morphology band height (rows)
     int32_t delta, S1, open_it, close_it, min_area, fill_pm, glo, ghi;
+    int32_t scaled;            // thresholds scaled by the gain instead of corrected pixels
+    uint32_t S_q16;            // max(S * 2^16, 1): the gray tolerance against (max - min) * inv
     HueTest hue;
     // accumulators (zero when the table is uploaded)
     // gain sums over usable sampled pixels, sampled row r adding to slot

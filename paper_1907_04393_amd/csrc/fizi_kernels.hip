@@ -405,6 +405,8 @@ struct ClsJob {
     const GLOBAL uint32_t *fr, *mn, *mx;
     GLOBAL uint64_t *raw;
     int delta, S1;
+    int scaled;
+    uint32_t S_q16;
     HueTest h;
 };
 
@@ -417,6 +419,8 @@ __device__ __forceinline__ ClsJob cls_job(const Job *J)
     c.raw = G(J->raw);
     c.delta = J->delta;
     c.S1 = J->S1;
+    c.scaled = J->scaled;
+    c.S_q16 = J->S_q16;
     c.h = J->hue;
     return c;
 }
@@ -444,15 +448,42 @@ __device__ __forceinline__ void load_px4(const ClsJob &c, uint32_t p, uint32_t p
 // I_R1, I_R2 and I_R3 of one 1024-pixel unit of a frame (256 per wave, 4 per
 // lane) whose pixels from pend on are not classified; base is the wave's
 // first pixel (a multiple of 64), raw words at or past pend / 64 are not
-// written; x holds the lane's inputs (loaded by load_px4).
-template <bool FLOW>
+// written; x holds the lane's inputs (loaded by load_px4). SCALED: the
+// thresholds follow the frame's brightness and the pixels stay raw.
+template <bool FLOW, bool SCALED>
 __device__ __forceinline__ void classify_px4(const ClsJob &c, uint32_t base, uint32_t pend, uint32_t inv,
                                              const Px4 &x)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t p = base + 4u * lane;
     uint32_t bits = 0;
-    if (p < pend) {
+    if (SCALED && p < pend) {
+        // (bgmin - delta) 2^16 <= v inv <= (bgmax + delta) 2^16 as one
+        // unsigned compare of v inv + (delta - bgmin) 2^16 (wrapping below
+        // zero) against (bgmax - bgmin + 2 delta) 2^16; v inv < 2^28
+        int cv[12];
+        uint32_t out = 0;
+        const uint32_t rng[3] = {x.u[0] - x.l[0], x.u[1] - x.l[1], x.u[2] - x.l[2]};
+        const uint32_t kd = (uint32_t)c.delta << 16, d2 = 2u * (uint32_t)c.delta;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const uint32_t v = byte_of(x.f[0], x.f[1], x.f[2], i);
+            const uint32_t d = __umul24(v, inv) + kd - (byte_of(x.l[0], x.l[1], x.l[2], i) << 16);
+            cv[i] = (int)v;
+            out |= (uint32_t)(d > ((byte_of(rng[0], rng[1], rng[2], i) + d2) << 16)) << (i / 3);
+        }
+        if (out) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (out & (1u << k)) {
+                    const int r = cv[3 * k], g = cv[3 * k + 1], b = cv[3 * k + 2];
+                    const uint32_t ch = (uint32_t)(max(max(r, g), b) - min(min(r, g), b));
+                    if (__umul24(ch, inv) >= c.S_q16 && hue_in(r, g, b, c.h))
+                        bits |= 1u << k;
+                }
+            }
+        }
+    } else if (!SCALED && p < pend) {
         // v' in [bgmin - delta, bgmax + delta] is one unsigned compare:
         // (v' + delta - bgmin) <= (bgmax - bgmin) + 2 delta, with v' + delta
         // from the correction's own multiply-add (delta << 16 added before the
@@ -496,8 +527,8 @@ __device__ __forceinline__ void classify_px4(const ClsJob &c, uint32_t base, uin
 // The wave's units of pixels [p0, p1) of a frame (p0 a multiple of 64):
 // 1024 pixels apart, each unit's inputs loaded one unit ahead into
 // alternating registers.
-template <bool FLOW>
-__device__ __forceinline__ void classify_span(const ClsJob &c, uint32_t p0, uint32_t p1, uint32_t inv)
+template <bool FLOW, bool SCALED>
+__device__ __forceinline__ void classify_span_as(const ClsJob &c, uint32_t p0, uint32_t p1, uint32_t inv)
 {
     const uint32_t lanepx = 4u * (threadIdx.x & (kWave - 1));
     uint32_t base = p0 + (uint32_t)(threadIdx.x / kWave) * 256u;
@@ -505,14 +536,23 @@ __device__ __forceinline__ void classify_span(const ClsJob &c, uint32_t p0, uint
     load_px4(c, base + lanepx, p1, a);
     while (base < p1) {
         load_px4(c, base + 1024u + lanepx, p1, b);
-        classify_px4<FLOW>(c, base, p1, inv, a);
+        classify_px4<FLOW, SCALED>(c, base, p1, inv, a);
         base += 1024u;
         if (base >= p1)
             break;
         load_px4(c, base + 1024u + lanepx, p1, a);
-        classify_px4<FLOW>(c, base, p1, inv, b);
+        classify_px4<FLOW, SCALED>(c, base, p1, inv, b);
         base += 1024u;
     }
+}
+
+template <bool FLOW>
+__device__ __forceinline__ void classify_span(const ClsJob &c, uint32_t p0, uint32_t p1, uint32_t inv)
+{
+    if (c.scaled)
+        classify_span_as<FLOW, true>(c, p0, p1, inv);
+    else
+        classify_span_as<FLOW, false>(c, p0, p1, inv);
 }
 
 // Classify tile `tile` of frame j: ITERS consecutive 1024-pixel units.
@@ -531,7 +571,10 @@ __device__ __forceinline__ void classify_tile(Table *__restrict__ T, int j, int 
             break;
         Px4 x;
         load_px4(c, base + lanepx, npx, x);
-        classify_px4<false>(c, base, npx, inv, x);
+        if (c.scaled)
+            classify_px4<false, true>(c, base, npx, inv, x);
+        else
+            classify_px4<false, false>(c, base, npx, inv, x);
     }
 }
 

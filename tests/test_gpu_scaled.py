@@ -1,0 +1,98 @@
+"""GPU parity of the adaptive-threshold option (brightness_mode 1, reading
+R12: the box bounds and the gray tolerance follow the frame's gain, the pixels
+stay raw) with the CPU oracle: a scene with per-frame gain, forced gains with
+pixels crowded around the scaled bounds, and streams of both options mixed in
+one batch in every launch mode."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import compare, gpu_run, need_gpu, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def test_small_scene_scaled_thresholds():
+    from paper_1907_04393_amd import scene
+    sc = scene.Scene(scene.small_plain(seed_stream=3))
+    bg, hand = sc.bg_frames(0, 30), sc.hand_frames(0, 40)
+    print("small scene, brightness_mode 1", flush=True)
+    g = gpu_run(bg, hand, dict(brightness_mode=1), chunk=16)
+    m, outs = oracle_run(bg, hand, dict(brightness_mode=1))
+    compare(g, m, outs, "scaled")
+
+
+def _boundary_scene(W, H, seed):
+    """A background of skin and non-skin halves; running frames are the
+    background plus noise of +-14, so many channels straddle the box."""
+    rng = np.random.default_rng(seed)
+    base = rng.integers(20, 230, (H, W, 3))
+    base[:, : W // 2] = (rng.integers(150, 230, (H, W // 2, 1)) * np.array([1.0, 0.7, 0.45])).astype(int)
+    bg = np.clip(base[None] + rng.integers(-2, 3, (4, H, W, 3)), 0, 255).astype(np.uint8)
+    hand = np.clip(base[None] + rng.integers(-14, 15, (3, H, W, 3)), 0, 255).astype(np.uint8)
+    return torch.from_numpy(bg), torch.from_numpy(hand)
+
+
+@pytest.mark.parametrize("inv", [32768, 45000, 65536, 70001, 131072])
+@pytest.mark.parametrize("delta,S", [(7, 25), (0, 0)])
+def test_forced_gain_at_the_bounds(inv, delta, S):
+    """gain_lo = gain_hi forces the inverse gain; no morphology, so I_FIZI is
+    the AND of the three masks bit for bit."""
+    params = dict(brightness_mode=1, gain_lo_q16=inv, gain_hi_q16=inv, bg_delta=delta, gray_S=S,
+                  open_iters=0, close_iters=0)
+    print("forced gain", params, flush=True)
+    bg, hand = _boundary_scene(192, 37, seed=inv + delta)
+    g = gpu_run(bg, hand, params, chunk=2)
+    m, outs = oracle_run(bg, hand, params)
+    compare(g, m, outs, str(params))
+    assert all(0 < o["fizi"].sum() < o["fizi"].size for o in outs.values())
+    # away from unit gain the two options part on this scene
+    from oracle import oracle
+    m0 = oracle.Model(192, 37, oracle.params(**dict(params, brightness_mode=0)))
+    m0.learn(bg.numpy())
+    differs = any(not np.array_equal(m0.process(hand[k].numpy())["fizi"], outs[k]["fizi"]) for k in outs)
+    assert differs == (inv != 65536)
+
+
+@pytest.mark.parametrize("mode", (0, 1, 2, 3))
+def test_batch_mixes_both_options(mode):
+    from oracle import oracle
+    from paper_1907_04393_amd import fizi, scene
+    dev = need_gpu()
+    specs = [scene.SceneSpec(320, 240, sigma=3, seed=(9, 1, 0, 0), gain="drift"),
+             scene.SceneSpec(640, 480, sigma=4, seed=(9, 1, 0, 1), distractors=1),
+             scene.SceneSpec(128, 96, sigma=2, seed=(9, 1, 0, 2), gain="drift"),
+             scene.SceneSpec(64, 33, sigma=3, seed=(9, 1, 0, 3))]
+    params = [dict(brightness_mode=k % 2) for k in range(len(specs))]
+    print("batch mode", mode, "with both brightness options", flush=True)
+    b = fizi.Batch([(sp.width, sp.height) for sp in specs],
+                   [fizi.default_params(**p) for p in params], device=dev)
+    b.set_mode(mode)
+    data, orc = [], []
+    for i, (sp, pr) in enumerate(zip(specs, params)):
+        sc = scene.Scene(sp)
+        bg, hand = sc.bg_frames(0, 8), sc.hand_frames(0, 4)
+        b.learn(i, bg.to(dev))
+        m = oracle.Model(sp.width, sp.height, oracle.params(**pr))
+        m.learn(bg.numpy())
+        data.append(hand)
+        orc.append(m)
+    fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in specs]
+    for k in range(4):
+        ptrs = torch.empty((len(specs), 56), dtype=torch.uint8, device=dev)
+        b.step([h[k].to(dev) for h in data], ptrs, fizi=fz)
+        torch.cuda.synchronize()
+        got = fizi.pointers_to_numpy(ptrs)
+        for i, sp in enumerate(specs):
+            ref = orc[i].process(data[i][k].numpy(), frame_index=k)
+            assert fizi.pointer_dict(got[i]) == ref["pointer"], (mode, k, i)
+            assert np.array_equal(fizi.unpack_bits(fz[i], sp.width), ref["fizi"]), (mode, k, i)
+    assert b.status() == 0
+    b.close()
+
+
+def test_bad_brightness_mode_is_rejected():
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    with pytest.raises(fizi.FiziError):
+        fizi.Context(64, 8, fizi.default_params(brightness_mode=2), device=dev)
