@@ -62,6 +62,8 @@ typedef struct {
     int32_t gain_lo_q16;          /* clamp of the inverse gain, Q16 */
     int32_t gain_hi_q16;
     int32_t brightness_mode;      /* 0: correct the pixels, 1: scale the thresholds */
+    int32_t click_debounce;       /* tracked streams: frames a click change needs
+                                     (applied by the tracker of the Python oracle) */
 } orc_params;
 
 typedef struct {

@@ -5,7 +5,10 @@ benchmark's CPU-baseline leg. The GPU library never imports, links or runs
 anything under oracle/.
 
 Masks here are byte images (one uint8 0/1 per pixel, H x W); frames are
-H x W x 3 uint8 RGB.
+H x W x 3 uint8 RGB. Beside the wrappers, one step is written here in plain
+Python: the click debouncing of a tracked stream (ClickDebounce, reading R13:
+Section 2, the Mouse module tracks the hand and reports its click state),
+a state machine of two integers per stream.
 """
 from __future__ import annotations
 
@@ -22,7 +25,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # Defaults of the readings (hue interval, margins, morphology, click, gain).
 DEFAULTS = dict(alpha1_cdeg=33000, alpha2_cdeg=7500, gray_S=20, bg_delta=10,
                 open_iters=1, close_iters=1, min_area=1, click_fill_permille=700,
-                gain_row_stride=8, gain_lo_q16=32768, gain_hi_q16=131072, brightness_mode=0)
+                gain_row_stride=8, gain_lo_q16=32768, gain_hi_q16=131072, brightness_mode=0,
+                click_debounce=0)
 
 
 class Params(ctypes.Structure):
@@ -285,18 +289,45 @@ def centroid_pixel(ptr):
     return (ptr["sum_x"] // ptr["area"], ptr["sum_y"] // ptr["area"])
 
 
+class ClickDebounce:
+    """Click debouncing of a tracked stream (reading R13): the reported click
+    changes only once D consecutive frames show the new state; a frame
+    without a hand reports no click and clears the count. D <= 1 reports
+    every frame's own click."""
+
+    def __init__(self, D):
+        self.D = int(D)
+        self.click = 0   # the reported state
+        self.count = 0   # consecutive frames that disagree with it
+
+    def step(self, present, raw_click):
+        if not present:
+            self.click, self.count = 0, 0
+            return 0
+        if raw_click == self.click:
+            self.count = 0
+        else:
+            self.count += 1
+            if self.count >= self.D:
+                self.click, self.count = raw_click, 0
+        return self.click
+
+
 class Tracker:
     """Temporal tracking over a frame sequence (R10): each frame's hand is
     the component that covers the previous frame's centroid pixel when it is
-    large enough, else the largest."""
+    large enough, else the largest; its click is debounced (R13)."""
 
     def __init__(self, model):
         self.m = model
         self.prev = None
+        self.debounce = ClickDebounce(model.p.click_debounce)
 
     def process(self, frame, frame_index=0, want_hand=False):
         out = self.m.process(frame, frame_index, want_hand=want_hand, track=self.prev)
-        self.prev = centroid_pixel(out["pointer"])
+        ptr = out["pointer"]
+        ptr["click"] = self.debounce.step(ptr["present"], ptr["click"])
+        self.prev = centroid_pixel(ptr)
         return out
 
 

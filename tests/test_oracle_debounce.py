@@ -52,7 +52,7 @@ def test_isolated_flips_never_pass():
 
 
 def _shapes():
-    """A filled square (fill 1: click) and a hollow one (fill 0.36: no click)
+    """A filled square (fill 1: click) and a hollow one (fill 0.64: no click)
     at a slowly moving position."""
     W, H = 128, 64
     seq = "FFHFFHHHFHHH"
