@@ -100,6 +100,12 @@ typedef struct {
      * against bound * 2^16); the hue is the raw pixel's. The gain itself and
      * the learning (on corrected frames) do not change. */
     int32_t brightness_mode;   /* 0 or 1 */
+    /* Section 2, the Mouse module tracks the hand and its state: with
+     * temporal tracking on, the reported click changes only once
+     * click_debounce consecutive frames show the new state; a frame without
+     * a hand reports no click and clears the count. 0..255, default 0
+     * (0 and 1 report every frame's own click). No effect without tracking. */
+    int32_t click_debounce;
 } fizi_params;
 
 /* One frame's pointer (56 bytes). When `present` is 0 every field except

@@ -118,6 +118,7 @@ int fizi_default_params(fizi_params *out)
     out->gain_lo_q16 = 32768;
     out->gain_hi_q16 = 131072;
     out->brightness_mode = 0;
+    out->click_debounce = 0;
     return FIZI_OK;
 }
 

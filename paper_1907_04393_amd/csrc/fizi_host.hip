@@ -94,6 +94,8 @@ int validate(const fizi_geom *g, const fizi_params *p)
         return fail(FIZI_EINVAL, "need 1 <= gain_lo_q16 <= gain_hi_q16 <= 2^20");
     if (p->brightness_mode != 0 && p->brightness_mode != 1)
         return fail(FIZI_EINVAL, "brightness_mode must be 0 or 1");
+    if (p->click_debounce < 0 || p->click_debounce > 255)
+        return fail(FIZI_EINVAL, "click_debounce must be in 0..255");
     return FIZI_OK;
 }
 
@@ -191,6 +193,7 @@ void fill_job(const Model &m, int band, Job &J)
     J.ghi = m.p.gain_hi_q16;
     J.scaled = m.p.brightness_mode;
     J.S_q16 = std::max((uint32_t)m.p.gray_S << 16, 1u);
+    J.debounce = m.p.click_debounce;
     J.hue = m.hue;
     J.track = m.tracking ? m.track : nullptr;
 }

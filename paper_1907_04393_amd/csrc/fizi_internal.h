@@ -47,9 +47,12 @@ struct HueTest {
 };
 
 // Temporal tracking state of one stream (device memory): the previous
-// frame's centroid pixel, valid when that frame had a hand.
+// frame's centroid pixel, valid when that frame had a hand, and the click
+// debouncer (bit 0: the reported click; bits 8..15: consecutive frames whose
+// own click differs from it).
 struct TrackState {
-    int32_t valid, x, y, pad;
+    int32_t valid, x, y;
+    uint32_t click;
 };
 
 struct Job {
@@ -75,6 +78,7 @@ struct Job {
     int32_t delta, S1, open_it, close_it, min_area, fill_pm, glo, ghi;
     int32_t scaled;            // thresholds scaled by the gain instead of corrected pixels
     uint32_t S_q16;            // max(S * 2^16, 1): the gray tolerance against (max - min) * inv
+    int32_t debounce;          // tracked streams: frames a change of the click needs
     HueTest hue;
     // accumulators (zero when the table is uploaded)
     // gain sums over usable sampled pixels, sampled row r adding to slot

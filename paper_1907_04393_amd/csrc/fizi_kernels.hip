@@ -1451,6 +1451,23 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
         o.n_components = ncomp;
         o.inv_gain_q16 = inv;
         o.frame_index = J->frame_index;
+        if (J->track) {
+            // click debouncing: a change is reported once `debounce`
+            // consecutive frames show it; no hand clears the count
+            TrackState *ts = J->track;
+            uint32_t shown = ts->click & 1u, count = (ts->click >> 8) & 0xFFu;
+            if (!present) {
+                shown = 0;
+                count = 0;
+            } else if (o.click == shown) {
+                count = 0;
+            } else if (++count >= (uint32_t)J->debounce) {
+                shown = o.click;
+                count = 0;
+            }
+            o.click = (uint8_t)shown;
+            ts->click = shown | (count << 8);
+        }
         *J->out = o;
         if (J->track) {
             TrackState *ts = J->track;

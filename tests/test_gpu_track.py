@@ -141,3 +141,82 @@ def test_batch_tracking_matches_oracle(mode):
         assert got[1] == mb.process(frb[k].numpy(), frame_index=k)["pointer"], (mode, k)
     assert b.status() == 0
     b.close()
+
+
+SHAPES = "FFHFFHHHFHHH"   # filled square (clicks) / hollow square (does not)
+
+
+def _shape_frames():
+    masks = []
+    for k, s in enumerate(SHAPES):
+        m = np.zeros((H, W), np.uint8)
+        x0 = 20 + 2 * k
+        m[10:40, x0:x0 + 30] = 1
+        if s == "H":
+            m[16:34, x0 + 6:x0 + 24] = 0
+        masks.append(m)
+    bg = np.zeros((2, H, W, 3), np.uint8)
+    bg[...] = (40, 40, 90)
+    fr = np.repeat(bg[:1], len(masks), axis=0).copy()
+    fr[np.stack(masks).astype(bool)] = (210, 140, 90)
+    return torch.from_numpy(bg), torch.from_numpy(fr)
+
+
+@pytest.mark.parametrize("D,chunk", [(2, 1), (2, 5), (3, 12), (0, 4)])
+def test_plain_click_debounce_matches_oracle(D, chunk):
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    params = dict(PARAMS, click_debounce=D)
+    bg, fr = _shape_frames()
+    ref = _oracle_track(bg, fr, params)
+    assert [r["pointer"]["click"] for r in ref] != [int(s == "F") for s in SHAPES] or D == 0
+    ctx = fizi.Context(W, H, fizi.default_params(**params), chunk=chunk, device=dev)
+    ctx.learn_background(bg.to(dev))
+    ctx.set_tracking(True)
+    out = ctx.process_frames(fr.to(dev))
+    torch.cuda.synchronize()
+    got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(out["pointers"])]
+    for k in range(len(SHAPES)):
+        assert got[k] == ref[k]["pointer"], (D, chunk, k)
+    # re-enabling clears the debouncer: two filled frames are needed again
+    ctx.set_tracking(True)
+    out = ctx.process_frames(fr[:2].to(dev))
+    torch.cuda.synchronize()
+    clicks = [int(r["click"]) for r in fizi.pointers_to_numpy(out["pointers"])]
+    assert clicks == ([1, 1] if D <= 1 else [0, 1] if D == 2 else [0, 0])
+    # without tracking the setting has no effect
+    ctx.set_tracking(False)
+    out = ctx.process_frames(fr.to(dev))
+    torch.cuda.synchronize()
+    assert [int(r["click"]) for r in fizi.pointers_to_numpy(out["pointers"])] == [int(s == "F") for s in SHAPES]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_batch_click_debounce_matches_oracle(mode):
+    from oracle import oracle
+    from paper_1907_04393_amd import fizi
+    from test_gpu_plain import _blob_scene
+    dev = need_gpu()
+    params = dict(PARAMS, click_debounce=2)
+    bg, fr = _shape_frames()
+    bgb, frb = _blob_scene(192, 70, 4, len(SHAPES), seed=23)
+    b = fizi.Batch([(W, H), (192, 70)], [fizi.default_params(**params), fizi.default_params(click_debounce=3)],
+                   device=dev)
+    b.set_mode(mode)
+    b.learn(0, bg.to(dev))
+    b.learn(1, bgb.to(dev))
+    b.set_tracking(0, True)
+    ref_a = _oracle_track(bg, fr, params)
+    mb = oracle.Model(192, 70, oracle.params(click_debounce=3))
+    mb.learn(bgb.numpy())
+    fa, fb = fr.to(dev), frb.to(dev)
+    for k in range(len(SHAPES)):
+        ptrs = torch.empty((2, 56), dtype=torch.uint8, device=dev)
+        b.step([fa[k], fb[k]], ptrs)
+        torch.cuda.synchronize()
+        got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(ptrs)]
+        assert got[0] == ref_a[k]["pointer"], (mode, k)
+        # stream 1 is not tracked: its clicks are the frame's own
+        assert got[1] == mb.process(frb[k].numpy(), frame_index=k)["pointer"], (mode, k)
+    assert b.status() == 0
+    b.close()
