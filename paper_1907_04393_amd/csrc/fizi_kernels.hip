@@ -164,6 +164,22 @@ __device__ __forceinline__ bool hue_in(int r, int g, int b, const HueTest &h)
     return (d1 == 0) & (3 * dp - __mul24(h.dsum, r + g + b) > 0);
 }
 
+// hue_in with the interval's case fixed at compile time (no branch on it).
+template <int MODE>
+__device__ __forceinline__ bool hue_in_mode(int r, int g, int b, const HueTest &h)
+{
+    const int rb = r - b, gb = g - b;
+    const int d1 = __mul24(h.k1r, rb) + __mul24(h.k1g, gb);
+    if constexpr (MODE == 1)
+        return (d1 >= 0) & (__mul24(h.k2r, rb) + __mul24(h.k2g, gb) <= 0);
+    if constexpr (MODE == 3)
+        return (d1 >= 0) | (__mul24(h.k2r, rb) + __mul24(h.k2g, gb) <= 0);
+    if constexpr (MODE == 2)
+        return d1 >= 0;
+    const int dp = __mul24(h.dr, r) + __mul24(h.dg, g) + __mul24(h.db, b);
+    return (d1 == 0) & (3 * dp - __mul24(h.dsum, r + g + b) > 0);
+}
+
 __device__ __forceinline__ uint32_t byte_of(uint32_t w0, uint32_t w1, uint32_t w2, int i)
 {
     const uint32_t w = i < 4 ? w0 : (i < 8 ? w1 : w2);
@@ -220,7 +236,8 @@ __global__ __launch_bounds__(256) void k_make_yref(const uint8_t *__restrict__ f
 // ---------------------------------------------------------------------------
 // One sampled row of one frame: sums of reference and frame luminance over
 // its usable pixels, added to the frame's accumulators.
-__device__ __forceinline__ void gain_tile(Table *__restrict__ T, int j, int tile)
+template <int MODE>
+__device__ __forceinline__ void gain_tile_mode(Table *__restrict__ T, int j, int tile)
 {
     __shared__ uint32_t s_num[256 / kWave], s_den[256 / kWave];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -230,19 +247,17 @@ __device__ __forceinline__ void gain_tile(Table *__restrict__ T, int j, int tile
     const HueTest h = J->hue;
     uint32_t num = 0, den = 0;
     const int r0 = tile * kGainRows, nr = min(rows, r0 + kGainRows) - r0;
-    // one usable-pixel test, summed into num/den
+    // one usable-pixel test, summed into num/den; straight-line code (every
+    // test evaluated, the sums selected) rather than a branch per pixel
     auto add_px = [&](uint32_t r, uint32_t gg, uint32_t b, uint32_t y) {
-        bool ok = (y != kYrefClipped) & (r - 1u < 254u) & (gg - 1u < 254u) & (b - 1u < 254u);
-        if (ok) {
-            const int mx = max(max((int)r, (int)gg), (int)b);
-            const int mn = min(min((int)r, (int)gg), (int)b);
-            if (mx > mn && hue_in((int)r, (int)gg, (int)b, h))
-                ok = false;
-        }
-        if (ok) {
-            num += y;
-            den += r + 2 * gg + b;
-        }
+        const int mx = max(max((int)r, (int)gg), (int)b);
+        const int mn = min(min((int)r, (int)gg), (int)b);
+        // every channel in 1..254
+        const bool unclipped = (y != kYrefClipped) & (mn >= 1) & (mx <= 254);
+        const bool skin = (mx > mn) & hue_in_mode<MODE>((int)r, (int)gg, (int)b, h);
+        const bool ok = unclipped & !skin;
+        num += ok ? y : 0u;
+        den += ok ? r + 2 * gg + b : 0u;
     };
     if ((reinterpret_cast<uintptr_t>(J->frame) & 15u) == 0) {
         // 16 pixels per item: three 16-byte loads of the frame row, two of
@@ -323,6 +338,25 @@ __device__ __forceinline__ void for_block_tiles(const int32_t *pre, int nj, F f)
         while (t >= pre[j + 1])
             ++j;
         f(j, t - pre[j]);
+    }
+}
+
+// A gain tile, its hue test's case chosen once per tile.
+__device__ __forceinline__ void gain_tile(Table *__restrict__ T, int j, int tile)
+{
+    switch (T->jobs[j].hue.mode) {
+    case 0:
+        gain_tile_mode<0>(T, j, tile);
+        break;
+    case 1:
+        gain_tile_mode<1>(T, j, tile);
+        break;
+    case 2:
+        gain_tile_mode<2>(T, j, tile);
+        break;
+    default:
+        gain_tile_mode<3>(T, j, tile);
+        break;
     }
 }
 
@@ -680,17 +714,37 @@ __device__ __forceinline__ int next_zero(P row, int Wd, int pos)
 // Union-find over run starts (pixel indices). A parent never exceeds its
 // child, so following parents always ends, and the root of a finished
 // component is its smallest run start: its first pixel in raster order.
+// Root of x with path halving: each visited node is pointed at its
+// grandparent. Safe beside concurrent finds and unions of the same workgroup:
+// parents only ever move to ancestors of the same set (a linked root's new
+// parent is smaller, a halved node's grandparent is one of its ancestors), so
+// a store that overwrites another still leaves the node in its set. Without
+// it, the border joins of a tall component chain one band's root under the
+// next, and every find walks that chain one dependent load at a time.
 __device__ __forceinline__ uint32_t find_root(GLOBAL uint32_t *parent, uint32_t x)
 {
-    uint32_t p = ld_wg(parent + x);
-    while (p != x) {
-        x = p;
-        p = ld_wg(parent + x);
+    for (;;) {
+        const uint32_t p = ld_wg(parent + x);
+        if (p == x)
+            return x;
+        const uint32_t g = ld_wg(parent + p);
+        if (g == p)
+            return p;
+        st_wg(parent + x, g);
+        x = g;
     }
-    return x;
 }
 
-__device__ __forceinline__ void unite(GLOBAL uint32_t *parent, uint32_t a, uint32_t b)
+// Roots that a workgroup's unions link under another root, kept so that the
+// chains they form can be flattened afterwards (a list that overflows only
+// leaves some chains as they are).
+constexpr int kLinkedMax = 2048;
+struct LinkedRoots {
+    uint32_t n;
+    uint32_t root[kLinkedMax];
+};
+
+__device__ __forceinline__ void unite(GLOBAL uint32_t *parent, uint32_t a, uint32_t b, LinkedRoots &rec)
 {
     for (;;) {
         a = find_root(parent, a);
@@ -704,9 +758,39 @@ __device__ __forceinline__ void unite(GLOBAL uint32_t *parent, uint32_t a, uint3
         }
         const uint32_t old = __hip_atomic_fetch_min(parent + b, a, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (old == b)
+        if (old == b) {
+            const uint32_t k = atomicAdd(&rec.n, 1u);
+            if (k < (uint32_t)kLinkedMax)
+                rec.root[k] = b;
             return;
+        }
         b = old;
+    }
+}
+
+// Pointer jumping over the linked roots: every round points each at its
+// grandparent, with a barrier between rounds, until none moves. Concurrent
+// unions link each band's root under the previous band's, so a tall
+// component leaves a chain as long as it has bands; jumping shortens every
+// chain by half per round, and afterwards a run is at most two steps from its
+// root (its segment root, then the component's). Rounds are capped; finds
+// stay correct on whatever is left.
+__device__ __forceinline__ void flatten_linked(GLOBAL uint32_t *parent, const LinkedRoots &rec)
+{
+    const uint32_t n = min(rec.n, (uint32_t)kLinkedMax);
+    for (int round = 0; round < 32; ++round) {
+        int moved = 0;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t b = rec.root[i];
+            const uint32_t p = ld_wg(parent + b);
+            const uint32_t g = ld_wg(parent + p);
+            if (g != p) {
+                st_wg(parent + b, g);
+                moved = 1;
+            }
+        }
+        if (!__syncthreads_or(moved))
+            break;
     }
 }
 
@@ -714,7 +798,7 @@ __device__ __forceinline__ void unite(GLOBAL uint32_t *parent, uint32_t a, uint3
 // row above that it touches under 8-connectivity (columns xs-1 .. xe+1).
 template <typename P>
 __device__ __forceinline__ void link_up(GLOBAL uint32_t *parent, P above, int Wd, int W, int y,
-                                        int xs, int xe, uint32_t start)
+                                        int xs, int xe, uint32_t start, LinkedRoots &rec)
 {
     const int hi = min(xe + 1, W - 1);
     int pos = max(xs - 1, 0);
@@ -723,7 +807,7 @@ __device__ __forceinline__ void link_up(GLOBAL uint32_t *parent, P above, int Wd
         if (xb < 0)
             break;
         const int bs = prev_zero(above, xb) + 1;
-        unite(parent, start, (uint32_t)(y - 1) * (uint32_t)W + (uint32_t)bs);
+        unite(parent, start, (uint32_t)(y - 1) * (uint32_t)W + (uint32_t)bs, rec);
         pos = next_zero(above, Wd, xb) + 1;
     }
 }
@@ -1285,34 +1369,48 @@ __global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T)
 constexpr int kResolveThreads = 1024;
 constexpr int kMaxWaves = 16;
 
-template <typename T, typename Op>
-__device__ __forceinline__ T block_reduce(T v, T *s, Op op)
-{
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1)
-        v = op(v, (T)__shfl_xor(v, o, kWave));
-    if (lane == 0)
-        s[wave] = v;
-    __syncthreads();
-    T r = s[0];
-    for (int w = 1; w < (int)(blockDim.x / kWave); ++w)
-        r = op(r, s[w]);
-    __syncthreads();
-    return r;
-}
+// Component areas of one frame, summed in LDS: an open-addressing table from
+// root to area. A component's runs all add to its root, and same-address
+// atomics serialise far less in LDS than in the cache (a hand is a thousand
+// runs on a 4K frame). A root that finds no free slot in its probe window
+// adds in global memory instead, and so do all of its runs, since slots are
+// only ever taken: the table and the global array never share a root.
+constexpr int kAreaSlots = 2048;
+constexpr int kAreaProbe = 32;
+constexpr uint32_t kAreaEmpty = 0xFFFFFFFFu;
+struct AreaTable {
+    uint32_t key[kAreaSlots];
+    uint32_t val[kAreaSlots];
+    uint32_t overflow;
+};
+// the persistent step lends its four waves' morphology tables to it
+static_assert(sizeof(AreaTable) <= 4 * sizeof(WaveLds), "area table fits the morphology LDS");
 
-struct OpAdd { template <typename T> __device__ T operator()(T a, T b) const { return a + b; } };
-struct OpMax { template <typename T> __device__ T operator()(T a, T b) const { return a > b ? a : b; } };
-struct OpMin { template <typename T> __device__ T operator()(T a, T b) const { return a < b ? a : b; } };
+__device__ __forceinline__ void area_add(AreaTable &t, GLOBAL uint32_t *area, uint32_t root, uint32_t len)
+{
+    uint32_t slot = (root * 2654435761u) >> (32 - 11);
+    for (int p = 0; p < kAreaProbe; ++p) {
+        uint32_t k = __hip_atomic_load(&t.key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == kAreaEmpty)
+            k = atomicCAS(&t.key[slot], kAreaEmpty, root);
+        if (k == kAreaEmpty || k == root) {
+            atomicAdd(&t.val[slot], len);
+            return;
+        }
+        slot = (slot + 1u) & (uint32_t)(kAreaSlots - 1);
+    }
+    t.overflow = 1u;
+    __hip_atomic_fetch_add(area + root, len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 // One workgroup per frame: joins the band-local trees across band borders,
 // then finds roots, areas, the hand zone (largest area, ties to the smallest
 // first index), its sums and box, and writes the pointer.
-__device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool same_launch)
+__device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool same_launch, AreaTable &tab)
 {
-    __shared__ unsigned long long s_u64[kMaxWaves];
-    __shared__ uint32_t s_u32[kMaxWaves];
+    __shared__ unsigned long long s_u64[2][kMaxWaves];
+    __shared__ uint32_t s_u32[5][kMaxWaves];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
     Job *J = &T->jobs[j];
     const int W = J->W, H = J->H, Wd = J->Wd;
     const uint32_t nr = min(ld_dev(&J->nruns), J->run_cap);
@@ -1327,11 +1425,21 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
             hand[i] = 0ull;
     // A: joins across band and segment borders (pairs of run starts), and
     // runs flagged when the pair list was full, joined by reading I_FIZI
+    __shared__ LinkedRoots s_rec;
+    if (threadIdx.x == 0) {
+        s_rec.n = 0;
+        tab.overflow = 0;
+    }
+    for (int i = threadIdx.x; i < kAreaSlots; i += blockDim.x) {
+        tab.key[i] = kAreaEmpty;
+        tab.val[i] = 0;
+    }
+    __syncthreads();
     const uint32_t nl = min(ld_dev(&J->nlinks), J->link_cap);
     const GLOBAL uint64_t *links = G(reinterpret_cast<const uint64_t *>(J->links));
     for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
         const uint64_t l = links[i];
-        unite(parent, (uint32_t)l, (uint32_t)(l >> 32));
+        unite(parent, (uint32_t)l, (uint32_t)(l >> 32), s_rec);
     }
     if (ld_dev(&J->nflag))
         for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
@@ -1343,9 +1451,10 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
             if (y == 0)
                 continue;
             const int xs = (int)(rn.x - (uint32_t)y * W), xe = xs + (int)rn.y - 1;
-            link_up(parent, fz + (size_t)(y - 1) * Wd, Wd, W, y, xs, xe, rn.x);
+            link_up(parent, fz + (size_t)(y - 1) * Wd, Wd, W, y, xs, xe, rn.x, s_rec);
         }
     __syncthreads();
+    flatten_linked(parent, s_rec);
     // B: roots and areas
     uint32_t ncomp = 0;
     for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
@@ -1355,20 +1464,54 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
             ++ncomp;
         else
             st_wg(parent + rn.x, root);
-        __hip_atomic_fetch_add(area + root, rn.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        area_add(tab, area, root, rn.y);
     }
     __syncthreads();
-    // C: the largest component, ties to the smallest first index
+    // the table's areas go to the global array (the tracking test reads it)
+    for (int i = threadIdx.x; i < kAreaSlots; i += blockDim.x) {
+        const uint32_t k = tab.key[i];
+        if (k != kAreaEmpty)
+            st_wg(area + k, tab.val[i]);
+    }
+    // C: the largest component, ties to the smallest first index: from the
+    // table, or from every run when some root did not fit it
     unsigned long long best = 0ull;
-    for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
-        const uint32_t s = (uint32_t)runs[i];
-        if (ld_wg(parent + s) == s) {
-            const unsigned long long key = ((unsigned long long)ld_wg(area + s) << 32) | (0xFFFFFFFFull - s);
-            best = key > best ? key : best;
+    if (!tab.overflow) {
+        for (int i = threadIdx.x; i < kAreaSlots; i += blockDim.x) {
+            const uint32_t k = tab.key[i];
+            if (k != kAreaEmpty) {
+                const unsigned long long key = ((unsigned long long)tab.val[i] << 32) | (0xFFFFFFFFull - k);
+                best = key > best ? key : best;
+            }
+        }
+    } else {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+            const uint32_t s = (uint32_t)runs[i];
+            if (ld_wg(parent + s) == s) {
+                const unsigned long long key = ((unsigned long long)ld_wg(area + s) << 32) | (0xFFFFFFFFull - s);
+                best = key > best ? key : best;
+            }
         }
     }
-    best = block_reduce<unsigned long long>(best, s_u64, OpMax());
-    ncomp = block_reduce<uint32_t>(ncomp, s_u32, OpAdd());
+    // one pass for both: per wave, then across the waves
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const unsigned long long ob = __shfl_xor(best, o, kWave);
+        best = ob > best ? ob : best;
+        ncomp += (uint32_t)__shfl_xor((int)ncomp, o, kWave);
+    }
+    if (lane == 0) {
+        s_u64[0][wave] = best;
+        s_u32[0][wave] = ncomp;
+    }
+    __syncthreads();
+    best = s_u64[0][0];
+    ncomp = s_u32[0][0];
+    for (int w = 1; w < nw; ++w) {
+        best = s_u64[0][w] > best ? s_u64[0][w] : best;
+        ncomp += s_u32[0][w];
+    }
     // temporal tracking: the component that covers the previous frame's
     // centroid pixel keeps the hand when its area reaches min_area
     __shared__ uint32_t s_pick;
@@ -1423,13 +1566,34 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
             }
         }
     }
-    sx = block_reduce<unsigned long long>(sx, s_u64, OpAdd());
-    sy = block_reduce<unsigned long long>(sy, s_u64, OpAdd());
-    x0 = block_reduce<uint32_t>(x0, s_u32, OpMin());
-    y0 = block_reduce<uint32_t>(y0, s_u32, OpMin());
-    x1 = block_reduce<uint32_t>(x1, s_u32, OpMax());
-    y1 = block_reduce<uint32_t>(y1, s_u32, OpMax());
+    // sums and box in one pass: per wave, then thread 0 across the waves
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        sx += __shfl_xor(sx, o, kWave);
+        sy += __shfl_xor(sy, o, kWave);
+        x0 = min(x0, (uint32_t)__shfl_xor((int)x0, o, kWave));
+        y0 = min(y0, (uint32_t)__shfl_xor((int)y0, o, kWave));
+        x1 = max(x1, (uint32_t)__shfl_xor((int)x1, o, kWave));
+        y1 = max(y1, (uint32_t)__shfl_xor((int)y1, o, kWave));
+    }
+    if (lane == 0) {
+        s_u64[0][wave] = sx;
+        s_u64[1][wave] = sy;
+        s_u32[1][wave] = x0;
+        s_u32[2][wave] = y0;
+        s_u32[3][wave] = x1;
+        s_u32[4][wave] = y1;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; ++w) {
+            sx += s_u64[0][w];
+            sy += s_u64[1][w];
+            x0 = min(x0, s_u32[1][w]);
+            y0 = min(y0, s_u32[2][w]);
+            x1 = max(x1, s_u32[3][w]);
+            y1 = max(y1, s_u32[4][w]);
+        }
         fizi_pointer o;
         o.present = present ? 1 : 0;
         o.click = 0;
@@ -1483,9 +1647,10 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
 
 __global__ __launch_bounds__(kResolveThreads) void k_resolve(Table *__restrict__ T)
 {
+    __shared__ AreaTable s_tab;
     const int nj = T->h.njobs;
     for (int j = blockIdx.x; j < nj; j += gridDim.x)
-        resolve_job(T, j, false);
+        resolve_job(T, j, false, s_tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -1608,7 +1773,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX == 4 &
             if (publish_add(&J->morph_done, cnt, &s_u) + cnt == (uint32_t)nsub) {
                 // the frame's last band: its components
                 acquire_for_block();
-                resolve_job(T, j, true);
+                // the waves' morphology tables are free again: the area table
+                // takes their place
+                resolve_job(T, j, true, *reinterpret_cast<AreaTable *>(&s_wl[0]));
             }
         }
     }

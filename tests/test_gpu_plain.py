@@ -272,3 +272,43 @@ def test_unaligned_frames_are_rejected():
     with pytest.raises(fizi.FiziError) as e:
         ctx.process_frames(_offset_copy(hand, 2, dev))
     assert e.value.code == fizi.FIZI_EINVAL
+
+
+def _mask_frames(masks):
+    """Frames that classify to exactly the given masks: a flat blue
+    background and skin-coloured foreground."""
+    n, H, W = masks.shape
+    bg = np.zeros((2, H, W, 3), np.uint8)
+    bg[...] = (40, 40, 90)
+    fr = np.repeat(bg[:1], n, axis=0).copy()
+    fr[masks.astype(bool)] = (210, 140, 90)
+    return torch.from_numpy(bg), torch.from_numpy(fr)
+
+
+@pytest.mark.parametrize("kind", ["comb", "bars", "serpentine"])
+def test_tall_components_many_border_joins(kind):
+    """Components that cross every band border many times: thousands of
+    cross-band joins (more than the resolve stage's list of linked roots
+    holds), long root chains, one or hundreds of components."""
+    W, H = 2048, 1024
+    m = np.zeros((H, W), np.uint8)
+    if kind == "comb":
+        m[:, 0:W:4] = 1
+        m[:, 1:W:4] = 1
+        m[H - 3:, :] = 1                      # the bars joined at the bottom
+    elif kind == "bars":
+        m[:, 0:W:4] = 1
+    else:
+        for k, x in enumerate(range(0, W, 8)):
+            m[:, x:x + 2] = 1
+            y = H - 2 if k % 2 == 0 else 0    # joined alternately at the bottom and top
+            m[y:y + 2, x:x + 10] = 1
+    masks = np.stack([m, m[::-1].copy()])
+    bg, fr = _mask_frames(masks)
+    params = dict(open_iters=0, close_iters=0)
+    print("tall components", kind, flush=True)
+    g = gpu_run(bg, fr, params, chunk=2)
+    mo, outs = oracle_run(bg, fr, params)
+    compare(g, mo, outs, kind)
+    expect = {"comb": 1, "bars": W // 4, "serpentine": 1}[kind]
+    assert all(o["pointer"]["n_components"] == expect for o in outs.values())
