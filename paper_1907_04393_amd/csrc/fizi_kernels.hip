@@ -1122,13 +1122,15 @@ __device__ __forceinline__ void load_rows(uint64_t (&dst)[kRawChunk][NC], const 
 }
 
 // KMAX: most opening/closing stages a job may have; NC: words per lane; FLOW:
-// inside the persistent step (stores other workgroups read in the launch).
-template <int KMAX, int NC, bool FLOW>
+// inside the persistent step (stores other workgroups read in the launch);
+// OI, CI: the opening and closing iterations when fixed at compile time (the
+// stages' kinds then need no selects), -1 to read them from the job.
+template <int KMAX, int NC, bool FLOW, int OI = -1, int CI = -1>
 __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int W = J->W, H = J->H, Wd = J->Wd, R = J->band;
-    const int oi = J->open_it, ci = J->close_it;
+    const int oi = OI >= 0 ? OI : J->open_it, ci = CI >= 0 ? CI : J->close_it;
     const int K = 2 * (oi + ci);
     const int y0 = band * R, y1 = min(y0 + R, H);
     // one more halo row above: row y0 - 1 is computed exactly, to join the
@@ -1361,7 +1363,11 @@ __global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T)
     for (int t = blockIdx.x * (256 / kWave) + wave; t < total; t += gridDim.x * (256 / kWave))
     {
         const int j = find_job(T->h.mor_pre, nj, t);
-        morph_band<KMAX, NC, false>(&T->jobs[j], t - T->h.mor_pre[j], s_wl[wave]);
+        Job *J = &T->jobs[j];
+        if (KMAX >= 4 && J->open_it == 1 && J->close_it == 1)   // the default opening and closing
+            morph_band<KMAX, NC, false, 1, 1>(J, t - T->h.mor_pre[j], s_wl[wave]);
+        else
+            morph_band<KMAX, NC, false>(J, t - T->h.mor_pre[j], s_wl[wave]);
     }
 }
 
