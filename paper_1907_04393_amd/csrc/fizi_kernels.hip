@@ -565,7 +565,7 @@ template <bool FLOW, bool SCALED>
 __device__ __forceinline__ void classify_span_as(const ClsJob &c, uint32_t p0, uint32_t p1, uint32_t inv)
 {
     const uint32_t lanepx = 4u * (threadIdx.x & (kWave - 1));
-    uint32_t base = p0 + (uint32_t)(threadIdx.x / kWave) * 256u;
+    uint32_t base = p0 + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) * 256u;
     Px4 a, b;
     load_px4(c, base + lanepx, p1, a);
     while (base < p1) {
@@ -593,7 +593,7 @@ __device__ __forceinline__ void classify_span(const ClsJob &c, uint32_t p0, uint
 template <int ITERS>
 __device__ __forceinline__ void classify_tile(Table *__restrict__ T, int j, int tile, uint32_t inv)
 {
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const Job *J = &T->jobs[j];
     const uint32_t npx = (uint32_t)J->W * (uint32_t)J->H;
     const ClsJob c = cls_job(J);
@@ -1357,7 +1357,9 @@ template <int KMAX, int NC>
 __global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T)
 {
     __shared__ WaveLds s_wl[256 / kWave];
-    const int wave = threadIdx.x / kWave;
+    // wave-uniform, and known to be: the band, its job and everything derived
+    // from them then live in scalar registers, with scalar branches
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int nj = T->h.njobs;
     const int total = T->h.mor_pre[nj];
     for (int t = blockIdx.x * (256 / kWave) + wave; t < total; t += gridDim.x * (256 / kWave))
@@ -1718,7 +1720,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX == 4 &
     __shared__ WaveLds s_wl[256 / kWave];
     __shared__ int s_item;
     __shared__ uint32_t s_u;
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int nseg = T->h.flow_nseg;
     const int total = T->h.flow_pre[nseg];
     int k = 0;
