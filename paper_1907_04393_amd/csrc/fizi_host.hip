@@ -183,6 +183,10 @@ void fill_job(const Model &m, int band, Job &J)
     J.Wd = m.g.width / 64;
     J.rs = m.p.gain_row_stride;
     J.band = band;
+    // narrow frames under the default opening and closing share a wave
+    // between bands: 4 bands of at most 16 words, or 2 of at most 32
+    const bool packable = m.p.open_iters == 1 && m.p.close_iters == 1;
+    J.mgroup = !packable ? 64 : (J.Wd <= 16 ? 16 : (J.Wd <= 32 ? 32 : 64));
     J.delta = m.p.bg_delta;
     J.S1 = std::max(m.p.gray_S, 1);
     J.open_it = m.p.open_iters;
@@ -222,7 +226,8 @@ void set_prefixes(Table &T, int njobs, const Tuning &t)
         const int rows = (J.H + J.rs - 1) / J.rs;
         T.h.gain_pre[i + 1] = T.h.gain_pre[i] + (rows + kGainRows - 1) / kGainRows;
         T.h.cls_pre[i + 1] = T.h.cls_pre[i] + (int)((px + ctile - 1) / ctile);
-        T.h.mor_pre[i + 1] = T.h.mor_pre[i] + (J.H + t.morph_rows - 1) / t.morph_rows;
+        const int bands = (J.H + t.morph_rows - 1) / t.morph_rows, per = 64 / J.mgroup;
+        T.h.mor_pre[i + 1] = T.h.mor_pre[i] + (bands + per - 1) / per;
     }
     // the persistent step's queue: jobs by size, largest first; every gain
     // tile ahead of the bands, so that a band rarely waits for its frame's

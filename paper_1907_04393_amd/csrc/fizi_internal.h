@@ -75,6 +75,7 @@ struct Job {
     uint32_t run_cap, link_cap;
     uint32_t epoch;            // this dispatch's number for its scratch slot (never 0)
     int32_t band;              // morphology band height (rows)
+    int32_t mgroup;            // morphology lanes per row: 64, or 16 / 32 to pack 4 / 2 bands per wave
     int32_t delta, S1, open_it, close_it, min_area, fill_pm, glo, ghi;
     int32_t scaled;            // thresholds scaled by the gain instead of corrected pixels
     uint32_t S_q16;            // max(S * 2^16, 1): the gray tolerance against (max - min) * inv
@@ -102,7 +103,7 @@ struct TableHeader {
     int32_t flow_nseg;                    // 2 * njobs
     int32_t gain_pre[kMaxJobs + 1];   // gain tiles (kGainRows sampled rows)
     int32_t cls_pre[kMaxJobs + 1];    // classify tiles
-    int32_t mor_pre[kMaxJobs + 1];    // morphology bands
+    int32_t mor_pre[kMaxJobs + 1];    // morphology items (64 / mgroup bands each)
     int32_t flow_pre[2 * kMaxJobs + 1];   // first item of each queue segment
     int32_t flow_seg[2 * kMaxJobs];       // (job << 1) | (0: gain, 1: bands)
 };

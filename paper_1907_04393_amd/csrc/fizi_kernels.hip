@@ -878,13 +878,22 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
+// Lanes per row: LG lanes hold one row (LG = 64: the whole wave; LG = 16 or
+// 32 pack 64 / LG bands of a narrow frame into one wave, lane group g holding
+// band g's row). The word a lane holds, and its group:
+template <int LG>
+__device__ __forceinline__ int lane_word() { return (int)(threadIdx.x & (uint32_t)(LG - 1)); }
+template <int LG>
+__device__ __forceinline__ int lane_group() { return LG == kWave ? 0 : (int)((threadIdx.x & (kWave - 1)) / LG); }
+
 // Edge bits of the neighbouring words of this lane's NC words (word
-// lane + 64 q): bit 63 of the word on the left (lc) and bit 0 of the word on
-// the right (rc); words outside [0, Wd) give `edge`.
-template <int NC>
+// w + 64 q of the lane group's row): bit 63 of the word on the left (lc) and
+// bit 0 of the word on the right (rc); words outside [0, Wd) give `edge`.
+template <int NC, int LG = kWave>
 __device__ __forceinline__ void row_carries(const uint64_t *v, int Wd, uint32_t edge, uint32_t *lc, uint32_t *rc)
 {
-    const int lane = threadIdx.x & (kWave - 1);
+    static_assert(NC == 1 || LG == kWave, "lane groups hold one word per lane");
+    const int lane = lane_word<LG>();
     const uint32_t hi0 = (uint32_t)(v[0] >> 63), lo0 = (uint32_t)v[0] & 1u;
     const uint32_t up0 = from_left(hi0), dn0 = from_right(lo0);
     lc[0] = lane == 0 ? edge : up0;
@@ -902,7 +911,7 @@ __device__ __forceinline__ void row_carries(const uint64_t *v, int Wd, uint32_t 
 }
 
 // One erosion (ero) or dilation of row b given the rows above (a) and below (c).
-template <int NC>
+template <int NC, int LG = kWave>
 __device__ __forceinline__ void morph_row(bool ero, const uint64_t *a, const uint64_t *b, const uint64_t *c, int Wd,
                                           uint64_t *out)
 {
@@ -911,7 +920,7 @@ __device__ __forceinline__ void morph_row(bool ero, const uint64_t *a, const uin
     for (int q = 0; q < NC; ++q)
         v[q] = ero ? (a[q] & b[q] & c[q]) : (a[q] | b[q] | c[q]);
     uint32_t lc[NC], rc[NC];
-    row_carries<NC>(v, Wd, ero ? 1u : 0u, lc, rc);
+    row_carries<NC, LG>(v, Wd, ero ? 1u : 0u, lc, rc);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
         const uint64_t left = (v[q] << 1) | lc[q];
@@ -991,12 +1000,14 @@ struct RowBits {
     int last[NC];
 };
 
-// Fills r from the row x; en receives the run ends. Returns the row's runs.
-template <int NC>
+// Fills r from the row x; en receives the run ends. Returns the row's runs
+// (of every lane group: runs are numbered across the wave). r.last holds
+// wave positions 64 lane + bit, which grow across the groups.
+template <int NC, int LG = kWave>
 __device__ __forceinline__ uint32_t row_bits(RowBits<NC> &r, const uint64_t *x, int Wd, uint64_t *en)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    row_carries<NC>(x, Wd, 0u, r.lc, r.rc);
+    row_carries<NC, LG>(x, Wd, 0u, r.lc, r.rc);
     uint32_t total = 0;
     int before = -1;
 #pragma unroll
@@ -1017,13 +1028,15 @@ __device__ __forceinline__ uint32_t row_bits(RowBits<NC> &r, const uint64_t *x, 
 }
 
 // x of the first pixel of the run that contains bit t (set, t in [-1, 64])
-// around word c of the row.
-template <int NC>
+// around word c of the row. A run never crosses a lane group (its edges are
+// out-of-image), so a start before the word lies in the same group.
+template <int NC, int LG = kWave>
 __device__ __forceinline__ int start_at(const RowBits<NC> &r, int c, int t)
 {
-    const int wb = 64 * ((int)(threadIdx.x & (kWave - 1)) + kWave * c);
+    const int wb = 64 * (lane_word<LG>() + kWave * c);
+    const int gofs = 64 * LG * lane_group<LG>();
     if (t < 0)
-        return r.last[c];
+        return r.last[c] - gofs;
     uint64_t m;
     if (t > 63) {
         if (r.rc[c] & ~(uint32_t)(r.w[c] >> 63) & 1u)
@@ -1032,36 +1045,66 @@ __device__ __forceinline__ int start_at(const RowBits<NC> &r, int c, int t)
     } else {
         m = r.st[c] & (~0ull >> (63 - t));
     }
-    return m ? wb + 63 - __builtin_clzll(m) : r.last[c];
+    return m ? wb + 63 - __builtin_clzll(m) : r.last[c] - gofs;
 }
 
 // Every touching pair of runs of two consecutive rows U (above) and D
-// (below), from the lanes' words: each run start looks at the one to three
-// pixels of the other row within one column. f(c, from_d, b, t): the run
-// starting at bit b of word c of D (from_d) or U touches the run of the other
-// row that contains bit t.
-template <int NC, typename F>
+// (below), each once, from the lanes' words. Under 8-connectivity a U run
+// [us, ue] and a D run [ds, de] touch when us <= de + 1 and ue >= ds - 1.
+// When us <= ds + 1, U has a pixel in columns ds - 1 .. ds + 1, and D's start
+// meets it there (the pixel at ds, else those beside it). Otherwise
+// us >= ds + 2, so D holds columns us - 2 and us - 1, and U's start meets the
+// D run there. f(c, from_d, b, t): the run starting at bit b of word c of D
+// (from_d) or U touches the run of the other row that contains bit t.
+// ONCE = false: U's starts look at the one to three pixels below them as D's
+// do above, so most pairs come twice (the band-border joins keep that form:
+// the component stage unites them concurrently, and the second meeting of a
+// pair shortens the chains the first one built).
+template <int NC, bool ONCE, typename F>
 __device__ __forceinline__ void touching_runs(const RowBits<NC> &U, const RowBits<NC> &D, F f)
 {
+    const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const RowBits<NC> &A = side == 0 ? D : U;   // starts
-            const RowBits<NC> &B = side == 0 ? U : D;   // the other row
-            uint64_t m = A.st[c];
-            while (m) {
-                const int b = __builtin_ctzll(m);
-                m &= m - 1;
-                if (bit_at(b, B.w[c], B.lc[c], B.rc[c])) {
-                    f(c, side == 0, b, b);
-                } else {
-                    if (bit_at(b - 1, B.w[c], B.lc[c], B.rc[c]))
-                        f(c, side == 0, b, b - 1);
-                    if (bit_at(b + 1, B.w[c], B.lc[c], B.rc[c]))
-                        f(c, side == 0, b, b + 1);
-                }
+        uint64_t m = D.st[c];
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            if (bit_at(b, U.w[c], U.lc[c], U.rc[c])) {
+                f(c, true, b, b);
+            } else {
+                if (bit_at(b - 1, U.w[c], U.lc[c], U.rc[c]))
+                    f(c, true, b, b - 1);
+                if (bit_at(b + 1, U.w[c], U.lc[c], U.rc[c]))
+                    f(c, true, b, b + 1);
             }
+        }
+        m = U.st[c];
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            if (!ONCE) {
+                if (bit_at(b, D.w[c], D.lc[c], D.rc[c])) {
+                    f(c, false, b, b);
+                } else {
+                    if (bit_at(b - 1, D.w[c], D.lc[c], D.rc[c]))
+                        f(c, false, b, b - 1);
+                    if (bit_at(b + 1, D.w[c], D.lc[c], D.rc[c]))
+                        f(c, false, b, b + 1);
+                }
+                continue;
+            }
+            // D holds columns b - 2 and b - 1 (for b = 0: its run through
+            // the word's left edge started at least two columns before it)
+            bool left2;
+            if (b >= 2)
+                left2 = ((D.w[c] >> (b - 2)) & 3ull) == 3ull;
+            else if (b == 1)
+                left2 = (D.lc[c] & (uint32_t)D.w[c] & 1u) != 0u;
+            else
+                left2 = D.lc[c] != 0u && D.last[c] < 64 * (lane + kWave * c) - 1;
+            if (left2)
+                f(c, false, b, b - 1);
         }
     }
 }
@@ -1102,19 +1145,20 @@ __device__ __forceinline__ void flush_segment(Job *J, WaveLds &L, uint32_t n, GL
     wave_sync();
 }
 
-// Rows r0 .. r0 + kRawChunk - 1 of the raw mask, addresses clamped to rows
-// below yb and words below Wd. Values of clamped rows and words are never
-// used (rows from yb on enter the pipeline as its neutral value, words from Wd
-// on never reach a valid word), so the loads need no condition: they stay in
-// flight while the previous chunk is processed.
-template <int NC>
-__device__ __forceinline__ void load_rows(uint64_t (&dst)[kRawChunk][NC], const GLOBAL uint64_t *raw, int r0, int yb,
+// Rows r0 .. r0 + kRawChunk - 1 of the raw mask (r0 per lane group),
+// addresses clamped to rows 0 .. H - 1 and words below Wd. Values of clamped
+// rows and words are never used (rows outside the image enter the pipeline as
+// its neutral value, words from Wd on never reach a valid word), so the loads
+// need no condition: they stay in flight while the previous chunk is
+// processed.
+template <int NC, int LG = kWave>
+__device__ __forceinline__ void load_rows(uint64_t (&dst)[kRawChunk][NC], const GLOBAL uint64_t *raw, int r0, int H,
                                           int Wd)
 {
-    const int lane = threadIdx.x & (kWave - 1);
+    const int lane = lane_word<LG>();
 #pragma unroll
     for (int qq = 0; qq < kRawChunk; ++qq) {
-        const size_t ro = (size_t)min(r0 + qq, yb - 1) * Wd;
+        const size_t ro = (size_t)min(max(r0 + qq, 0), H - 1) * Wd;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             dst[qq][c] = raw[ro + min(lane + kWave * c, Wd - 1)];
@@ -1124,18 +1168,22 @@ __device__ __forceinline__ void load_rows(uint64_t (&dst)[kRawChunk][NC], const 
 // KMAX: most opening/closing stages a job may have; NC: words per lane; FLOW:
 // inside the persistent step (stores other workgroups read in the launch);
 // OI, CI: the opening and closing iterations when fixed at compile time (the
-// stages' kinds then need no selects), -1 to read them from the job.
-template <int KMAX, int NC, bool FLOW, int OI = -1, int CI = -1>
+// stages' kinds then need no selects), -1 to read them from the job; LG:
+// lanes per row (bands band, band + 1, ... of the frame on the wave's lane
+// groups; every group steps through the same band-relative rows, so control
+// stays uniform, and rows outside the image are neutral or dropped per group).
+template <int KMAX, int NC, bool FLOW, int OI = -1, int CI = -1, int LG = kWave>
 __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
 {
     const int lane = threadIdx.x & (kWave - 1);
+    const int word = lane_word<LG>();
     const int W = J->W, H = J->H, Wd = J->Wd, R = J->band;
     const int oi = OI >= 0 ? OI : J->open_it, ci = CI >= 0 ? CI : J->close_it;
     const int K = 2 * (oi + ci);
-    const int y0 = band * R, y1 = min(y0 + R, H);
+    const int y0 = (band + lane_group<LG>()) * R;
     // one more halo row above: row y0 - 1 is computed exactly, to join the
     // band's first row to it without reading the band above
-    const int ya = max(0, y0 - K - 1), yb = min(H, y1 + K);
+    const int ya = y0 - K - 1;
     const GLOBAL uint64_t *raw = G(J->raw);
     GLOBAL uint64_t *fz = G(J->fizi);
     GLOBAL uint32_t *parent = G(J->parent);
@@ -1145,7 +1193,7 @@ __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
     bool valid_w[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q)
-        valid_w[q] = lane + kWave * q < Wd;
+        valid_w[q] = word + kWave * q < Wd;
 
     // pipeline state: the two rows before each stage's next input
     uint64_t p2[KMAX][NC], p1[KMAX][NC];
@@ -1166,11 +1214,11 @@ __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
     }
     GLOBAL uint32_t *linkw = G(reinterpret_cast<uint32_t *>(J->links));
     const uint32_t link_cap = J->link_cap;
-    const int nsteps = (y1 - ya) + K;
+    const int nsteps = R + 2 * K + 1;
     // one input row through the stages, then the band's final row it yields
     auto step = [&](int s, int q, const uint64_t (&ch)[kRawChunk][NC]) __attribute__((always_inline)) {
         uint64_t x[NC];
-        const bool past = ya + s >= yb;
+        const bool past = ya + s >= H;
         const uint64_t n0 = (K > 0 && stage_erodes(0, oi, ci)) ? ~0ull : 0ull;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -1188,7 +1236,7 @@ __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
                         x[c] = ero ? ~0ull : 0ull;
                 }
                 uint64_t o[NC];
-                morph_row<NC>(ero, p2[k], p1[k], x, Wd, o);
+                morph_row<NC, LG>(ero, p2[k], p1[k], x, Wd, o);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     p2[k][c] = p1[k][c];
@@ -1202,40 +1250,44 @@ __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
                     x[c] = oob ? n1 : o[c];
             }
         }
-        const int jrow = ya + s - K;
-        if (jrow < 0 || jrow < y0 - 1 || jrow >= y1)
+        // the row this step yields, relative to the band: -1 the halo row,
+        // 0 .. R - 1 the band's rows (outside the image: an empty row)
+        const int jrel = s - 2 * K - 1;
+        if (jrel < -1 || jrel >= R)
             return;
+        const int jrow = y0 + jrel;
+        const bool row_ok = jrow >= 0 && jrow < H;
         uint64_t orw = 0ull;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            if (!valid_w[c])
+            if (!valid_w[c] || !row_ok)
                 x[c] = 0ull;
             orw |= x[c];
         }
         const bool nonempty = __ballot(orw != 0ull) != 0ull;
-        if (jrow == y0 - 1) {
+        if (jrel == -1) {
             // the last row of the band above, only to join with
             if (nonempty) {
                 uint64_t en[NC];
-                (void)row_bits<NC>(P, x, Wd, en);
+                (void)row_bits<NC, LG>(P, x, Wd, en);
             }
             prev_valid = nonempty;
             prev_in_seg = false;
             return;
         }
         // a final I_FIZI row
-        GLOBAL uint64_t *frow = fz + (size_t)jrow * Wd;
+        GLOBAL uint64_t *frow = fz + (size_t)max(jrow, 0) * Wd;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (valid_w[c])
-                put<FLOW>(frow + lane + kWave * c, x[c]);
+            if (valid_w[c] && row_ok)
+                put<FLOW>(frow + word + kWave * c, x[c]);
         if (!nonempty) {
             prev_valid = false;
             return;
         }
         RowBits<NC> D;
         uint64_t en[NC];
-        const uint32_t total = row_bits<NC>(D, x, Wd, en);
+        const uint32_t total = row_bits<NC, LG>(D, x, Wd, en);
         if (nseg + total > (uint32_t)kSegRuns) {
             // the open segment is full: close it, this row opens the next
             flush_segment<FLOW>(J, L, nseg, runs, parent, area, cap);
@@ -1243,14 +1295,14 @@ __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
             prev_in_seg = false;
         }
         const bool direct = total > (uint32_t)kSegRuns;
-        const uint32_t rowpx = (uint32_t)jrow * (uint32_t)W;
+        const uint32_t rowpx = (uint32_t)max(jrow, 0) * (uint32_t)W;
         // joins with a row above whose runs are not in the open segment (the
         // band above, a closed segment, or a row written directly) go to the
         // frame's link list as pairs of run starts
         uint32_t flag = 0u;
         if (prev_valid && (!prev_in_seg || direct)) {
             uint32_t cnt = 0;
-            touching_runs<NC>(P, D, [&](int, bool, int, int) { ++cnt; });
+            touching_runs<NC, false>(P, D, [&](int, bool, int, int) { ++cnt; });
             const uint32_t inc = wave_incl_scan(cnt);
             const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
             uint32_t base = 0;
@@ -1259,11 +1311,11 @@ __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
             base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
             uint32_t k = base + inc - cnt;
             const uint32_t upx = rowpx - (uint32_t)W;
-            touching_runs<NC>(P, D, [&](int c, bool from_d, int b, int t) {
-                const uint32_t wb = 64u * (uint32_t)(lane + kWave * c);
+            touching_runs<NC, false>(P, D, [&](int c, bool from_d, int b, int t) {
+                const uint32_t wb = 64u * (uint32_t)(word + kWave * c);
                 const uint32_t a = from_d ? rowpx + wb + (uint32_t)b : upx + wb + (uint32_t)b;
-                const uint32_t o = from_d ? upx + (uint32_t)start_at<NC>(P, c, t)
-                                          : rowpx + (uint32_t)start_at<NC>(D, c, t);
+                const uint32_t o = from_d ? upx + (uint32_t)start_at<NC, LG>(P, c, t)
+                                          : rowpx + (uint32_t)start_at<NC, LG>(D, c, t);
                 if (k < link_cap) {
                     put<FLOW>(linkw + 2 * (size_t)k, a);
                     put<FLOW>(linkw + 2 * (size_t)k + 1, o);
@@ -1284,7 +1336,7 @@ __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
         // its start, the lane holding its last pixel its end
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const uint32_t wpx = rowpx + 64u * (uint32_t)(lane + kWave * c);
+            const uint32_t wpx = rowpx + 64u * (uint32_t)(word + kWave * c);
             uint64_t m = D.st[c];
             while (m) {
                 const int b = __builtin_ctzll(m);
@@ -1315,7 +1367,7 @@ __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
         wave_sync();
         // joins with the row above in the open segment, in the LDS union-find
         if (prev_valid && prev_in_seg && !direct) {
-            touching_runs<NC>(P, D, [&](int c, bool from_d, int b, int t) {
+            touching_runs<NC, true>(P, D, [&](int c, bool from_d, int b, int t) {
                 const uint64_t below = (1ull << b) - 1ull;
                 if (from_d)
                     unite_lds(L.par, nseg + D.ex[c] + (uint32_t)__popcll(D.st[c] & below),
@@ -1338,14 +1390,14 @@ __device__ __forceinline__ void morph_band(Job *J, int band, WaveLds &L)
     // input chunks alternate between two register buffers: each is loaded a
     // chunk ahead of its use, straight into the registers that use it
     uint64_t ca[kRawChunk][NC], cb[kRawChunk][NC];
-    load_rows<NC>(ca, raw, ya, yb, Wd);
+    load_rows<NC, LG>(ca, raw, ya, H, Wd);
 #pragma unroll 1
     for (int s0 = 0; s0 < nsteps; s0 += 2 * kRawChunk) {
-        load_rows<NC>(cb, raw, ya + s0 + kRawChunk, yb, Wd);
+        load_rows<NC, LG>(cb, raw, ya + s0 + kRawChunk, H, Wd);
 #pragma unroll 1
         for (int q = 0; q < kRawChunk && s0 + q < nsteps; ++q)
             step(s0 + q, q, ca);
-        load_rows<NC>(ca, raw, ya + s0 + 2 * kRawChunk, yb, Wd);
+        load_rows<NC, LG>(ca, raw, ya + s0 + 2 * kRawChunk, H, Wd);
 #pragma unroll 1
         for (int q = 0; q < kRawChunk && s0 + kRawChunk + q < nsteps; ++q)
             step(s0 + kRawChunk + q, q, cb);
@@ -1366,10 +1418,17 @@ __global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T)
     {
         const int j = find_job(T->h.mor_pre, nj, t);
         Job *J = &T->jobs[j];
-        if (KMAX >= 4 && J->open_it == 1 && J->close_it == 1)   // the default opening and closing
-            morph_band<KMAX, NC, false, 1, 1>(J, t - T->h.mor_pre[j], s_wl[wave]);
-        else
-            morph_band<KMAX, NC, false>(J, t - T->h.mor_pre[j], s_wl[wave]);
+        const int item = t - T->h.mor_pre[j];
+        if (KMAX >= 4 && J->open_it == 1 && J->close_it == 1) {   // the default opening and closing
+            if (J->mgroup == 16)
+                morph_band<KMAX, 1, false, 1, 1, 16>(J, 4 * item, s_wl[wave]);
+            else if (J->mgroup == 32)
+                morph_band<KMAX, 1, false, 1, 1, 32>(J, 2 * item, s_wl[wave]);
+            else
+                morph_band<KMAX, NC, false, 1, 1>(J, item, s_wl[wave]);
+        } else {
+            morph_band<KMAX, NC, false>(J, item, s_wl[wave]);
+        }
     }
 }
 
