@@ -312,3 +312,16 @@ def test_tall_components_many_border_joins(kind):
     compare(g, mo, outs, kind)
     expect = {"comb": 1, "bars": W // 4, "serpentine": 1}[kind]
     assert all(o["pointer"]["n_components"] == expect for o in outs.values())
+
+
+@pytest.mark.parametrize("W", [64, 960, 1024, 1088, 2048, 2112])
+@pytest.mark.parametrize("H", [1, 9, 40])
+def test_lane_group_boundaries(W, H):
+    """Morphology packs 4 bands per wave up to 16 words per row and 2 up to
+    32: widths on both sides of each limit, heights whose last item leaves
+    lane groups idle (1 and 9 rows: one or two bands of eight)."""
+    print(f"lane groups {W}x{H}", flush=True)
+    bg, hand = _blob_scene(W, H, 3, 3, seed=W + 7 * H)
+    g = gpu_run(bg, hand, {}, chunk=3)
+    m, outs = oracle_run(bg, hand, {})
+    compare(g, m, outs, f"{W}x{H}")
