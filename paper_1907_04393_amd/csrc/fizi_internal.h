@@ -118,7 +118,7 @@ static_assert(sizeof(TableHeader) % 8 == 0, "job array alignment");
 // Launch shapes (tunable per resolution class).
 struct Tuning {
     int cls_iters;      // classify tile = 1024 * cls_iters pixels (1, 2, 4, 8)
-    int morph_rows;     // morphology band height (16, 32, 64)
+    int morph_rows;     // morphology band height (8, 16, 32, 64)
     int grid_per_cu;    // resident blocks per CU for the streaming kernels
 };
 

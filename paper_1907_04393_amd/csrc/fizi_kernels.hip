@@ -2,19 +2,24 @@
 //
 //   k_make_yref  reference luminance of the sampled rows of the first
 //                learning frame (Section 2 initialisation, Section 3.2)
-//   k_gain       per-frame inverse gain from the sampled rows; the last block
-//                of each frame turns the two sums into the Q16 gain
-//   k_minmax     background learning: per-pixel, per-channel min/max of the
-//                gain-corrected frames, model read and written once
-//                (Section 3.1 (i))
-//   k_classify   gain correction, I_R1 (outside the learned box), I_R2 (not
-//                gray), I_R3 (skin hue), their AND, packed to bits with wave
-//                ballots (Section 3.1); HBM-bound, 4 pixels per lane
-//   k_morph      opening then closing with a 3x3 square on an LDS band of bit
-//                rows (64 pixels per operation), then run extraction
-//                (Section 3.1, last paragraph)
+//   k_gain       per-frame sums over the usable sampled pixels; each consumer
+//                turns a frame's sums into its Q16 inverse gain
+//   k_minmax     background learning and partial re-learning: per-pixel,
+//                per-channel min/max of the gain-corrected frames, model read
+//                and written once (Section 3.1 (i), Section 3.3)
+//   k_classify   gain correction (or thresholds scaled by the gain), I_R1
+//                (outside the learned box), I_R2 (not gray), I_R3 (skin hue),
+//                their AND, packed to bits with wave ballots (Sections 3.1,
+//                3.2); HBM-bound, 4 pixels per lane
+//   k_morph      opening then closing with a 3x3 square, streamed through a
+//                register pipeline of bit rows (64 pixels per lane word), then
+//                runs and band-local components in LDS (Section 3.1, last
+//                paragraph)
 //   k_resolve    8-connected components by union-find over runs, hand-zone
-//                selection and the pointer (Section 2, Mouse module)
+//                selection (largest, or tracked), the pointer (Section 2,
+//                Mouse module)
+//   k_flow       the persistent form of one step: gain tiles and row bands
+//                from one ordered queue, with bounded waits
 #include <hip/hip_ext.h>
 
 #include <algorithm>
