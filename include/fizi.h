@@ -360,8 +360,9 @@ typedef struct {
 
 /* Interface module (Section 2: "the interface zone activated by the
  * pointer"): h_zone[i] = the first zone, in array order, that holds pointer
- * i's position, or -1 (no hand, or no zone holds it). Host arrays;
- * synchronous. */
+ * i's position, or -1 (no hand, or no zone holds it). Host arrays owned by
+ * the caller (n pointers in, n zone indices out); synchronous, no GPU work.
+ * FIZI_EINVAL for a negative count or a null array with a nonzero count. */
 int fizi_zone_hit(const fizi_pointer *h_pointers, int32_t n, const fizi_zone *h_zones, int32_t n_zones,
                   int32_t *h_zone);
 
@@ -384,7 +385,9 @@ typedef struct {
 
 /* Driving application (Section 4: the hand turns an imaginary wheel that
  * controls left, right and speed): one fizi_drive per pointer (all zero off
- * the wheel or without a hand). Host arrays; synchronous. */
+ * the wheel or without a hand). Host arrays owned by the caller; synchronous,
+ * no GPU work. FIZI_EINVAL for a negative count, a null argument or a wheel
+ * outside the ranges above. */
 int fizi_drive_of(const fizi_pointer *h_pointers, int32_t n, const fizi_wheel *wheel, fizi_drive *h_out);
 
 /* Message of the last failed call on this thread ("" if none). */
