@@ -256,3 +256,38 @@ def test_dense_masks_every_band_height():
                     assert np.array_equal(fizi.unpack_bits(fz[i], W), orc[i][k]["fizi"]), (mode, rows, k, kind)
             assert b.status() == 0
     b.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_wide_and_narrow_streams(mode):
+    """An 8192-pixel-wide stream beside narrow ones: the morphology launch
+    takes two words per lane, and the narrow frames' packed bands run inside
+    it with one."""
+    from oracle import oracle
+    from test_gpu_plain import _blob_scene
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    shapes = [(8192, 24), (640, 48), (1920, 33), (1280, 17)]
+    print("wide and narrow, mode", mode, flush=True)
+    b = fizi.Batch(shapes, device=dev)
+    b.set_mode(mode)
+    data, orc = [], []
+    for i, (W, H) in enumerate(shapes):
+        bg, hand = _blob_scene(W, H, 3, 3, seed=31 * i + W)
+        b.learn(i, bg.to(dev))
+        m = oracle.Model(W, H)
+        m.learn(bg.numpy())
+        data.append(hand)
+        orc.append(m)
+    fz = [torch.empty((H, W // 64), dtype=torch.int64, device=dev) for W, H in shapes]
+    for k in range(3):
+        ptrs = torch.empty((len(shapes), 56), dtype=torch.uint8, device=dev)
+        b.step([h[k].to(dev) for h in data], ptrs, fizi=fz)
+        torch.cuda.synchronize()
+        got = fizi.pointers_to_numpy(ptrs)
+        for i, (W, H) in enumerate(shapes):
+            ref = orc[i].process(data[i][k].numpy(), frame_index=k)
+            assert fizi.pointer_dict(got[i]) == ref["pointer"], (mode, k, i)
+            assert np.array_equal(fizi.unpack_bits(fz[i], W), ref["fizi"]), (mode, k, i)
+    assert b.status() == 0
+    b.close()

@@ -325,3 +325,15 @@ def test_lane_group_boundaries(W, H):
     g = gpu_run(bg, hand, {}, chunk=3)
     m, outs = oracle_run(bg, hand, {})
     compare(g, m, outs, f"{W}x{H}")
+
+
+@pytest.mark.parametrize("W", [4160, 8192])
+@pytest.mark.parametrize("params", [{}, dict(open_iters=2, close_iters=0)])
+def test_widest_frames(W, params):
+    """Rows of more than 64 words (two words per lane in the morphology),
+    up to the 8192-pixel limit."""
+    print(f"widest {W}", params, flush=True)
+    bg, hand = _blob_scene(W, 40, 3, 3, seed=W)
+    g = gpu_run(bg, hand, params, chunk=2)
+    m, outs = oracle_run(bg, hand, params)
+    compare(g, m, outs, f"{W} {params}")
