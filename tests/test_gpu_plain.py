@@ -337,3 +337,14 @@ def test_widest_frames(W, params):
     g = gpu_run(bg, hand, params, chunk=2)
     m, outs = oracle_run(bg, hand, params)
     compare(g, m, outs, f"{W} {params}")
+
+
+@pytest.mark.parametrize("W,H", [(64, 8192), (192, 8191)])
+def test_tallest_frames(W, H):
+    """The 8192-row limit on narrow frames (a thousand bands, four per wave),
+    with a ragged last band."""
+    print(f"tallest {W}x{H}", flush=True)
+    bg, hand = _blob_scene(W, H, 3, 2, seed=H + W)
+    g = gpu_run(bg, hand, {}, chunk=2)
+    m, outs = oracle_run(bg, hand, {})
+    compare(g, m, outs, f"{W}x{H}")
