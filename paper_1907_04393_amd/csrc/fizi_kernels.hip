@@ -740,16 +740,7 @@ __device__ __forceinline__ uint32_t find_root(GLOBAL uint32_t *parent, uint32_t 
     }
 }
 
-// Roots that a workgroup's unions link under another root, kept so that the
-// chains they form can be flattened afterwards (a list that overflows only
-// leaves some chains as they are).
-constexpr int kLinkedMax = 2048;
-struct LinkedRoots {
-    uint32_t n;
-    uint32_t root[kLinkedMax];
-};
-
-__device__ __forceinline__ void unite(GLOBAL uint32_t *parent, uint32_t a, uint32_t b, LinkedRoots &rec)
+__device__ __forceinline__ void unite(GLOBAL uint32_t *parent, uint32_t a, uint32_t b)
 {
     for (;;) {
         a = find_root(parent, a);
@@ -763,39 +754,9 @@ __device__ __forceinline__ void unite(GLOBAL uint32_t *parent, uint32_t a, uint3
         }
         const uint32_t old = __hip_atomic_fetch_min(parent + b, a, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (old == b) {
-            const uint32_t k = atomicAdd(&rec.n, 1u);
-            if (k < (uint32_t)kLinkedMax)
-                rec.root[k] = b;
+        if (old == b)
             return;
-        }
         b = old;
-    }
-}
-
-// Pointer jumping over the linked roots: every round points each at its
-// grandparent, with a barrier between rounds, until none moves. Concurrent
-// unions link each band's root under the previous band's, so a tall
-// component leaves a chain as long as it has bands; jumping shortens every
-// chain by half per round, and afterwards a run is at most two steps from its
-// root (its segment root, then the component's). Rounds are capped; finds
-// stay correct on whatever is left.
-__device__ __forceinline__ void flatten_linked(GLOBAL uint32_t *parent, const LinkedRoots &rec)
-{
-    const uint32_t n = min(rec.n, (uint32_t)kLinkedMax);
-    for (int round = 0; round < 32; ++round) {
-        int moved = 0;
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint32_t b = rec.root[i];
-            const uint32_t p = ld_wg(parent + b);
-            const uint32_t g = ld_wg(parent + p);
-            if (g != p) {
-                st_wg(parent + b, g);
-                moved = 1;
-            }
-        }
-        if (!__syncthreads_or(moved))
-            break;
     }
 }
 
@@ -803,7 +764,7 @@ __device__ __forceinline__ void flatten_linked(GLOBAL uint32_t *parent, const Li
 // row above that it touches under 8-connectivity (columns xs-1 .. xe+1).
 template <typename P>
 __device__ __forceinline__ void link_up(GLOBAL uint32_t *parent, P above, int Wd, int W, int y,
-                                        int xs, int xe, uint32_t start, LinkedRoots &rec)
+                                        int xs, int xe, uint32_t start)
 {
     const int hi = min(xe + 1, W - 1);
     int pos = max(xs - 1, 0);
@@ -812,7 +773,7 @@ __device__ __forceinline__ void link_up(GLOBAL uint32_t *parent, P above, int Wd
         if (xb < 0)
             break;
         const int bs = prev_zero(above, xb) + 1;
-        unite(parent, start, (uint32_t)(y - 1) * (uint32_t)W + (uint32_t)bs, rec);
+        unite(parent, start, (uint32_t)(y - 1) * (uint32_t)W + (uint32_t)bs);
         pos = next_zero(above, Wd, xb) + 1;
     }
 }
@@ -1497,11 +1458,8 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
             hand[i] = 0ull;
     // A: joins across band and segment borders (pairs of run starts), and
     // runs flagged when the pair list was full, joined by reading I_FIZI
-    __shared__ LinkedRoots s_rec;
-    if (threadIdx.x == 0) {
-        s_rec.n = 0;
+    if (threadIdx.x == 0)
         tab.overflow = 0;
-    }
     for (int i = threadIdx.x; i < kAreaSlots; i += blockDim.x) {
         tab.key[i] = kAreaEmpty;
         tab.val[i] = 0;
@@ -1511,7 +1469,7 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
     const GLOBAL uint64_t *links = G(reinterpret_cast<const uint64_t *>(J->links));
     for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
         const uint64_t l = links[i];
-        unite(parent, (uint32_t)l, (uint32_t)(l >> 32), s_rec);
+        unite(parent, (uint32_t)l, (uint32_t)(l >> 32));
     }
     if (ld_dev(&J->nflag))
         for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
@@ -1523,10 +1481,9 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
             if (y == 0)
                 continue;
             const int xs = (int)(rn.x - (uint32_t)y * W), xe = xs + (int)rn.y - 1;
-            link_up(parent, fz + (size_t)(y - 1) * Wd, Wd, W, y, xs, xe, rn.x, s_rec);
+            link_up(parent, fz + (size_t)(y - 1) * Wd, Wd, W, y, xs, xe, rn.x);
         }
     __syncthreads();
-    flatten_linked(parent, s_rec);
     // B: roots and areas
     uint32_t ncomp = 0;
     for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
