@@ -243,9 +243,12 @@ class Context:
         self._check_frames(frames)
         n = int(frames.shape[0])
         shape = (n, self.height, self.width // 64)
-        fz = torch.empty(shape, dtype=torch.int64, device=self.device) if want_fizi else None
-        hd = torch.empty(shape, dtype=torch.int64, device=self.device) if want_hand else None
-        ptrs = torch.empty((n, 56), dtype=torch.uint8, device=self.device)
+        # the outputs are written on `stream`: allocated there, so that the
+        # caching allocator does not hand their memory out before it is done
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream(self.device)):
+            fz = torch.empty(shape, dtype=torch.int64, device=self.device) if want_fizi else None
+            hd = torch.empty(shape, dtype=torch.int64, device=self.device) if want_hand else None
+            ptrs = torch.empty((n, 56), dtype=torch.uint8, device=self.device)
         check(lib().process_frames(self._h, _ptr(frames), n, _ptr(fz), _ptr(hd), _ptr(ptrs),
                                    _stream(stream)))
         return dict(pointers=ptrs, fizi=fz, hand=hd)
@@ -358,18 +361,56 @@ class Batch:
         check(lib().fizi_batch_relearn(self._h, int(stream_id), _ptr(frames), n, _ptr(fizi_bits),
                                        _stream(stream)))
 
+    def _check_step(self, frames, pointers, fizi):
+        """The library sees only device addresses: every argument of a step
+        is checked against the batch's geometry here, before any is passed."""
+        if len(frames) != self.n:
+            raise FiziError(FIZI_EINVAL, f"a step takes {self.n} frame entries, got {len(frames)}")
+        for i, f in enumerate(frames):
+            if f is None:
+                continue
+            w, h = self.geoms[i]
+            if (not isinstance(f, torch.Tensor) or f.dtype != torch.uint8 or f.device != self.device
+                    or not f.is_contiguous() or tuple(f.shape) != (h, w, 3)):
+                raise FiziError(FIZI_EINVAL, f"frame {i} must be a contiguous uint8 ({h}, {w}, 3) "
+                                             f"tensor on {self.device}")
+        if (not isinstance(pointers, torch.Tensor) or pointers.dtype != torch.uint8
+                or pointers.device != self.device or not pointers.is_contiguous()
+                or tuple(pointers.shape) != (self.n, 56)):
+            raise FiziError(FIZI_EINVAL, f"pointers must be a contiguous uint8 ({self.n}, 56) tensor "
+                                         f"on {self.device}")
+        if fizi is not None:
+            if len(fizi) != self.n:
+                raise FiziError(FIZI_EINVAL, f"a step takes {self.n} mask entries, got {len(fizi)}")
+            for i, f in enumerate(fizi):
+                if f is None:
+                    continue
+                w, h = self.geoms[i]
+                if (not isinstance(f, torch.Tensor) or f.dtype != torch.int64 or f.device != self.device
+                        or not f.is_contiguous() or tuple(f.shape) != (h, w // 64)):
+                    raise FiziError(FIZI_EINVAL, f"mask {i} must be a contiguous int64 ({h}, {w // 64}) "
+                                                 f"tensor on {self.device}")
+
+    def _frame_array(self, frames):
+        """Every entry of the reusable ctypes array is set (NULL when idle)."""
+        for i in range(self.n):
+            f = frames[i]
+            self._frames[i] = f.data_ptr() if f is not None else None
+        return self._frames
+
     def step(self, frames, pointers: torch.Tensor, fizi=None, stream=None):
         """frames: list of n device frames (H, W, 3) uint8 or None (idle);
-        pointers: (n, 56) uint8 device tensor; fizi: optional list of bit
-        tensors (entries may be None)."""
-        for i, f in enumerate(frames):
-            self._frames[i] = f.data_ptr() if f is not None else None
+        pointers: (n, 56) uint8 device tensor; fizi: optional list of n bit
+        tensors (H, W/64) int64 (entries may be None)."""
+        self._check_step(frames, pointers, fizi)
+        fr = self._frame_array(frames)
         fz = None
         if fizi is not None:
-            for i, f in enumerate(fizi):
+            for i in range(self.n):
+                f = fizi[i]
                 self._fizi[i] = f.data_ptr() if f is not None else None
             fz = self._fizi
-        check(lib().fizi_batch_step(self._h, self._frames, fz, _ptr(pointers), _stream(stream)))
+        check(lib().fizi_batch_step(self._h, fr, fz, _ptr(pointers), _stream(stream)))
 
     def get_tuning(self) -> dict:
         t = Tuning()
@@ -383,10 +424,10 @@ class Batch:
     def autotune(self, frames, pointers, steps=5, stream=None):
         """Times candidate launch shapes on these frames; keeps the fastest.
         Returns (tuning dict, ms per step)."""
-        for i, f in enumerate(frames):
-            self._frames[i] = f.data_ptr() if f is not None else None
+        self._check_step(frames, pointers, None)
+        fr = self._frame_array(frames)
         t, ms = Tuning(), ctypes.c_double()
-        check(lib().fizi_batch_autotune(self._h, self._frames, _ptr(pointers), int(steps), _stream(stream),
+        check(lib().fizi_batch_autotune(self._h, fr, _ptr(pointers), int(steps), _stream(stream),
                                         ctypes.byref(t), ctypes.byref(ms)))
         return t.as_dict(), float(ms.value)
 

@@ -289,6 +289,13 @@ class GpuBackend:
         b, s = self.batches[lane], self.streams[lane]
         idx = self.lane_slots[lane]
         fr = [frames.get(i) for i in idx]
+        # frames may have been made on the current stream just now: the lane
+        # waits for them, and the allocator keeps their memory until the lane
+        # is done with it
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        for f in fr:
+            if f is not None:
+                f.record_stream(s)
         b.step(fr, self.ptrs[lane], stream=s)
         with torch.cuda.stream(s):
             self.host[lane].copy_(self.ptrs[lane], non_blocking=True)

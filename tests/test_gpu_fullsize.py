@@ -1,0 +1,150 @@
+"""Bit-exact parity at the full sizes of the benchmarked workloads, every
+output compared with the CPU oracle (Section 2 running phase; Section 3.1):
+
+* one 1920x1080 stream (sigma 5, two skin-coloured distractors): the model
+  learned from 50 user-free frames, then all 2000 hand frames, every I_FIZI
+  bit, every hand-zone bit and every pointer field;
+* the 64-stream batch (640x480 .. 3840x2160 drawn by seed): every stream's
+  model, then four frame steps of all 64 streams in every launch mode.
+
+The oracle runs on a pool of host threads (its C calls release the GIL);
+frames are rendered on the GPU and both sides consume the same bytes.
+"""
+import concurrent.futures as cf
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def _packed(mask):
+    """(H, W) 0/1 bytes -> (H, W/8) bytes in the device bit-row layout."""
+    return np.packbits(mask, axis=-1, bitorder="little")
+
+
+def _bytes(words):
+    """(..., H, W/64) int64 device words -> (..., H, W/8) host bytes."""
+    return words.cpu().numpy().view(np.uint8)
+
+
+@pytest.mark.timeout(900)
+def test_hd_stream_every_frame():
+    from oracle import oracle
+    from paper_1907_04393_amd import fizi, scene
+    dev = need_gpu()
+    spec = scene.hd_plain()
+    W, H = spec.width, spec.height
+    sc = scene.Scene(spec, device=dev)
+    bg = sc.bg_frames(0, spec.n_bg)
+    ctx = fizi.Context(W, H, chunk=scene.HD_CHUNK, device=dev)
+    ctx.learn_background(bg)
+    m = oracle.Model(W, H)
+    m.learn(bg.cpu().numpy())
+    bgmin, bgmax, yref = ctx.model()
+    assert np.array_equal(bgmin.cpu().numpy(), m.bgmin)
+    assert np.array_equal(bgmax.cpu().numpy(), m.bgmax)
+    assert np.array_equal(yref.cpu().numpy().view(np.uint16), m.yref)
+    del bg
+    chunk, present = 200, 0
+    with cf.ThreadPoolExecutor(THREADS) as pool:
+        for t0 in range(0, spec.n_hand, chunk):
+            t1 = min(spec.n_hand, t0 + chunk)
+            print(f"1920x1080 frames {t0}..{t1 - 1}", flush=True)
+            hand = sc.hand_frames(t0, t1)
+            out = ctx.process_frames(hand, want_fizi=True, want_hand=True)
+            torch.cuda.synchronize()
+            frames = hand.cpu().numpy()
+            ptrs = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(out["pointers"])]
+            fz, hd = _bytes(out["fizi"]), _bytes(out["hand"])
+
+            def check(k):
+                ref = m.process(frames[k], frame_index=t0 + k, want_hand=True)
+                if ptrs[k] != ref["pointer"]:
+                    return f"frame {t0 + k}: pointer {ptrs[k]} != {ref['pointer']}"
+                if not np.array_equal(fz[k], _packed(ref["fizi"])):
+                    return f"frame {t0 + k}: I_FIZI differs"
+                if not np.array_equal(hd[k], _packed(ref["hand"])):
+                    return f"frame {t0 + k}: hand zone differs"
+                return ref["pointer"]["present"]
+
+            res = list(pool.map(check, range(t1 - t0)))
+            bad = [r for r in res if isinstance(r, str)]
+            assert not bad, bad[:3]
+            present += sum(res)
+            del hand, out, frames
+    # the hand is found in (nearly) every frame of the sequence
+    assert present >= 0.95 * spec.n_hand
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def batched64():
+    """The 64-stream workload with four resident hand frames per stream, each
+    stream's learned model checked against the oracle's, and the oracle's
+    outputs for every frame of the pool."""
+    from oracle import oracle
+    from paper_1907_04393_amd import workloads
+    dev = need_gpu()
+    print("building the 64-stream workload", flush=True)
+    w = workloads.batched(64, pool=4, device=dev, log=lambda s: print(s, flush=True))
+    b = w["batch"]
+    models = [b.model(i) for i in range(len(w["specs"]))]
+    torch.cuda.synchronize()
+
+    def expect(i):
+        sp, sc = w["specs"][i], w["scenes"][i]
+        m = oracle.Model(sp.width, sp.height)
+        m.learn(sc.bg_frames(0, 30).cpu().numpy())
+        bgmin, bgmax, yref = models[i]
+        ok = (np.array_equal(bgmin.cpu().numpy(), m.bgmin) and np.array_equal(bgmax.cpu().numpy(), m.bgmax)
+              and np.array_equal(yref.cpu().numpy().view(np.uint16), m.yref))
+        frames = w["frames"][i].cpu().numpy()
+        outs = []
+        for k in range(w["pool"]):
+            ref = m.process(frames[k], frame_index=0)
+            p = dict(ref["pointer"])
+            p.pop("frame_index")
+            outs.append((p, _packed(ref["fizi"])))
+        return ok, outs
+
+    print("oracle: 64 models, 256 frames", flush=True)
+    with cf.ThreadPoolExecutor(THREADS) as pool:
+        res = list(pool.map(expect, range(len(w["specs"]))))
+    bad = [i for i, (ok, _) in enumerate(res) if not ok]
+    assert not bad, f"learned models differ from the oracle's for streams {bad}"
+    yield w, [outs for _, outs in res]
+    b.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mode", (1, 0, 2, 3))
+def test_batched_64_streams_every_output(batched64, mode):
+    from paper_1907_04393_amd import fizi, workloads
+    dev = need_gpu()
+    w, expected = batched64
+    b, specs = w["batch"], w["specs"]
+    n = len(specs)
+    b.set_mode(mode)
+    print("64 streams, launch mode", mode, b.get_tuning(), flush=True)
+    first = None
+    for k in range(4):
+        ptrs = torch.empty((n, 56), dtype=torch.uint8, device=dev)
+        fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in specs]
+        b.step(workloads.step_frames(w, k), ptrs, fizi=fz)
+        torch.cuda.synchronize()
+        got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(ptrs)]
+        if first is None:
+            first = got[0]["frame_index"]
+        for i in range(n):
+            assert got[i].pop("frame_index") == first + k, (mode, k, i)
+            p, bits = expected[i][k % w["pool"]]
+            assert got[i] == p, (mode, k, i, got[i], p)
+            assert np.array_equal(_bytes(fz[i]), bits), (mode, k, i)
+    assert b.status() == 0

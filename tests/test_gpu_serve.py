@@ -29,21 +29,35 @@ def _sessions(dev, n, dur, session_len=None, seed=0, rate=30.0):
 
 
 def _check_alone(sessions, results, dev):
+    """Every served pointer equals the oracle's for that session's learning
+    frames and the same hand frame, and the HIP plain path's for the frame
+    processed alone."""
+    from oracle import oracle
     from paper_1907_04393_amd import fizi
     by = {s.sid: s for s in sessions}
-    ctxs = {}
+    ctxs, models, seen = {}, {}, {}
     for r in results:
         s = by[r.sid]
         if r.sid not in ctxs:
+            bg = s.bg()
             c = fizi.Context(s.width, s.height, chunk=1, device=dev)
-            c.learn_background(s.bg())
+            c.learn_background(bg)
             ctxs[r.sid] = c
-        out = ctxs[r.sid].process_frames(s.frames(r.seq).unsqueeze(0).contiguous(), want_fizi=False)
+            m = oracle.Model(s.width, s.height)
+            m.learn(bg.cpu().numpy())
+            models[r.sid] = m
+        frame = s.frames(r.seq)
+        got = dict(r.pointer)
+        got["frame_index"] = 0
+        # the oracle, on the bytes the server processed
+        if (r.sid, r.seq % 4) not in seen:
+            seen[(r.sid, r.seq % 4)] = models[r.sid].process(frame.cpu().numpy(), frame_index=0)["pointer"]
+        assert got == seen[(r.sid, r.seq % 4)], ("oracle", r.sid, r.seq)
+        out = ctxs[r.sid].process_frames(frame.unsqueeze(0).contiguous(), want_fizi=False)
         torch.cuda.synchronize()
         ref = fizi.pointer_dict(fizi.pointers_to_numpy(out["pointers"])[0])
-        got = dict(r.pointer)
-        got["frame_index"] = ref["frame_index"] = 0
-        assert got == ref, (r.sid, r.seq)
+        ref["frame_index"] = 0
+        assert got == ref, ("alone", r.sid, r.seq)
 
 
 def test_mix_equals_alone():
@@ -59,6 +73,24 @@ def test_mix_equals_alone():
     assert {(r.sid, r.seq) for r in res} == want and len(res) == len(want)
     print("steps", srv.steps, "frames", len(res), "largest step", srv.max_step, flush=True)
     assert srv.max_step > 1 and srv.steps < len(res)
+    _check_alone(sessions, res, dev)
+    be.close()
+
+
+def test_frames_made_on_demand():
+    """Frames rendered on the current stream at the moment the server asks
+    for them (no pool made ahead): the lanes wait for them and keep their
+    memory alive, and the results still equal the oracle's."""
+    from paper_1907_04393_amd import serve
+    dev = need_gpu()
+    sessions, scenes = _sessions(dev, 4, 0.2, rate=500.0, seed=5)
+    for s, sc in zip(sessions, scenes):
+        s.frames = (lambda k, sc=sc: sc.hand_frame(k % 4))
+    be = serve.GpuBackend([(s.width, s.height) for s in sessions], lanes=2, device=dev)
+    srv = serve.Server(be)
+    res = srv.run(sessions, 0.2)
+    want = {(s.sid, k) for s in sessions for k in range(len(s.arrivals))}
+    assert {(r.sid, r.seq) for r in res} == want
     _check_alone(sessions, res, dev)
     be.close()
 
