@@ -740,6 +740,20 @@ __device__ __forceinline__ uint32_t find_root(GLOBAL uint32_t *parent, uint32_t 
     }
 }
 
+// Root of x without writing: once every find and union of a workgroup is
+// over, a node's parent need not be its root (a halving store of one thread
+// can land after another thread pointed the node at its root, and leave it at
+// an older ancestor), so a membership test walks to the root.
+__device__ __forceinline__ uint32_t root_of(GLOBAL uint32_t *parent, uint32_t x)
+{
+    for (;;) {
+        const uint32_t p = ld_wg(parent + x);
+        if (p == x)
+            return x;
+        x = p;
+    }
+}
+
 __device__ __forceinline__ void unite(GLOBAL uint32_t *parent, uint32_t a, uint32_t b)
 {
     for (;;) {
@@ -1573,7 +1587,7 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
     if (present) {
         for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
             const uint2 rn = unpack_run(runs[i]);
-            if (ld_wg(parent + rn.x) != kstar)
+            if (root_of(parent, rn.x) != kstar)
                 continue;
             const uint32_t y = rn.x / (uint32_t)W, xs = rn.x - y * (uint32_t)W;
             const uint32_t xe = xs + rn.y - 1;
