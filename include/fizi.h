@@ -238,7 +238,13 @@ enum {
     FIZI_BATCH_PERSISTENT = 2,        /* one persistent kernel per step, fed by an ordered
                                          work queue: gain tiles, row bands (classify, then
                                          morphology of the band above) and components overlap */
-    FIZI_BATCH_PERSISTENT_GRAPH = 3   /* the persistent kernel from a hipGraph */
+    FIZI_BATCH_PERSISTENT_GRAPH = 3,  /* the persistent kernel from a hipGraph */
+    FIZI_BATCH_PIPELINED = 4,         /* four kernels, software-pipelined across steps: a
+                                         step's gain and classify run on the caller's stream
+                                         beside the previous step's morphology, components
+                                         and pointers, which run on a second HIP stream
+                                         forked from and joined back to the caller's */
+    FIZI_BATCH_PIPELINED_GRAPH = 5    /* the same, replayed from hipGraphs */
 };
 
 /* Device bytes for n_streams (1..256) streams; geoms and params are arrays of
@@ -268,6 +274,17 @@ int fizi_batch_relearn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames
  * stream i has a frame. FIZI_ESTATE if an active stream has no model. Async. */
 int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *const *h_fizi_bits,
                     fizi_pointer *d_pointers, void *stream);
+
+/* In the pipelined modes a step's I_FIZI bits and pointers are written by
+ * the NEXT call that enqueues work on the batch: its next step (on that
+ * step's stream) or fizi_batch_flush. They are complete once that call's
+ * work has completed on its stream; until then the caller keeps the step's
+ * frame, bit-mask and pointer buffers alive and unread. Results are the same
+ * as in every other mode. fizi_batch_flush enqueues the pending half-step on
+ * `stream` (nothing to do in the other modes, or when nothing is pending).
+ * Learning, re-learning and the calls below that wait for pending steps
+ * flush first. Async. */
+int fizi_batch_flush(fizi_batch *b, void *stream);
 
 /* Selects how steps are launched (FIZI_BATCH_*); waits for pending steps. */
 int fizi_batch_set_mode(fizi_batch *b, int32_t mode);
@@ -312,7 +329,8 @@ int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t);
 int fizi_batch_autotune(fizi_batch *b, const uint8_t *const *h_frames, fizi_pointer *d_pointers,
                         int32_t steps, void *stream, fizi_tuning *best, double *best_ms);
 
-/* Waits for the batch's work and releases its host resources. */
+/* Waits for the batch's work and releases its host resources. A pipelined
+ * step still pending (not flushed) is dropped. */
 int fizi_batch_destroy(fizi_batch *b);
 
 /* ---- Differentiable form (calibration) -------------------------------------

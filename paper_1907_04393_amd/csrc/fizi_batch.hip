@@ -29,15 +29,34 @@ struct fizi_batch {
     hipEvent_t order_ev = nullptr;
     hipStream_t last_stream = nullptr;
     bool have_last = false;
+    // pipelined modes: a second raw-mask buffer per stream (steps alternate
+    // between the two, so that a step's classify never writes the bits its
+    // predecessor's morphology is reading), the side stream of the back
+    // halves and the stream of the table uploads, and per step parity the
+    // events that order them
+    std::vector<uint64_t *> raw2;
+    int parity = 0;
+    // graph form: the step whose back half is still to be enqueued
+    int pend_slot = -1, pend_jobs = 0;
+    // direct form: the parity of the step whose back half is enqueued on the
+    // side stream but not yet joined to a caller's stream
+    int pend_join = -1;
+    hipStream_t side = nullptr, up = nullptr;
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t up_ev[2] = {}, cls_ev[2] = {}, join_ev[2] = {};
+    hipGraphExec_t pgraph[kTabSlots][kTabSlots + 1] = {};   // by (slot, pending slot + 1)
 };
 
 namespace {
 
 struct BatchLayout {
     size_t tables, persist;
-    std::vector<size_t> model, slot;
+    std::vector<size_t> model, slot, raw2;
     size_t total;
 };
+
+bool is_pipelined(int mode) { return mode == FIZI_BATCH_PIPELINED || mode == FIZI_BATCH_PIPELINED_GRAPH; }
+bool is_persistent(int mode) { return mode == FIZI_BATCH_PERSISTENT || mode == FIZI_BATCH_PERSISTENT_GRAPH; }
 
 int check_streams(int32_t n, const fizi_geom *geoms, const fizi_params *params)
 {
@@ -60,11 +79,14 @@ BatchLayout batch_layout(int32_t n, const fizi_geom *geoms, const fizi_params *p
     off += align256(persist_state_bytes());
     L.model.resize(n);
     L.slot.resize(n);
+    L.raw2.resize(n);
     for (int i = 0; i < n; ++i) {
         L.model[i] = off;
         off += align256(model_bytes(geoms[i], params[i]));
         L.slot[i] = off;
         off += align256(slot_bytes(geoms[i]));
+        L.raw2[i] = off;
+        off += align256((size_t)geoms[i].height * (geoms[i].width / 64) * 8);
     }
     L.total = align256(off);
     return L;
@@ -101,6 +123,126 @@ int enqueue_step(fizi_batch *b, int slot, int njobs, bool fixed, hipStream_t s, 
                         clk);
 }
 
+// Pipelined step, graph form: the table upload, gain and classify of `slot`
+// on s and beside them, on the side stream, the morphology and components of
+// the pending step `pend` (none when negative); s then waits for the side
+// stream. The two halves touch disjoint memory: the front reads frames and
+// models and writes this step's raw bits and gain sums; the back reads the
+// other raw buffer and writes I_FIZI, the component scratch and the pointers.
+int enqueue_pipelined(fizi_batch *b, int slot, int njobs, int pend, int pend_jobs, bool fixed, hipStream_t s,
+                      hipStream_t side, StageClock *clk)
+{
+    const Table &T = *b->ring.h[slot];
+    if (pend >= 0) {
+        FIZI_HIP(hipEventRecord(b->fork_ev, s));
+        FIZI_HIP(hipStreamWaitEvent(side, b->fork_ev, 0));
+        FIZI_TRY(run_back(b->ring.d[pend], *b->ring.h[pend], pend_jobs, b->n, b->max_wd, b->max_ops, b->tune,
+                          b->n_cu, fixed, side, clk, true));
+        FIZI_HIP(hipEventRecord(b->join_ev[0], side));
+    }
+    FIZI_HIP(hipMemcpyAsync(b->ring.d[slot], &T, table_bytes(fixed ? b->n : njobs), hipMemcpyHostToDevice, s));
+    FIZI_TRY(run_front(b->ring.d[slot], T, njobs, b->tune, b->n_cu, fixed, s, clk));
+    if (pend >= 0)
+        FIZI_HIP(hipStreamWaitEvent(s, b->join_ev[0], 0));
+    return FIZI_OK;
+}
+
+int side_streams(fizi_batch *b)
+{
+    if (!b->side)
+        FIZI_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+    if (!b->up)
+        FIZI_HIP(hipStreamCreateWithFlags(&b->up, hipStreamNonBlocking));
+    return FIZI_OK;
+}
+
+// Pipelined step, direct form. The table goes up on its own stream (it
+// depends on nothing the device does), gain and classify follow on s, and
+// the back half is enqueued at once on the side stream behind classify:
+// it starts when classify ends, whether or not the next step has been
+// called, and runs beside the next step's gain and classify. s joins the
+// PREVIOUS step's back half after this classify (done by then, unless the
+// back half is the longer one), so the outputs of a step are ordered on s
+// after the next step, and the next classify never writes the raw buffer
+// that back half reads.
+int enqueue_pipelined_direct(fizi_batch *b, int slot, int njobs, hipStream_t s, StageClock *clk)
+{
+    const Table &T = *b->ring.h[slot];
+    const int par = b->parity;
+    FIZI_TRY(side_streams(b));
+    FIZI_HIP(hipMemcpyAsync(b->ring.d[slot], &T, table_bytes(njobs), hipMemcpyHostToDevice, b->up));
+    FIZI_HIP(hipEventRecord(b->up_ev[par], b->up));
+    FIZI_HIP(hipStreamWaitEvent(s, b->up_ev[par], 0));
+    FIZI_TRY(run_front(b->ring.d[slot], T, njobs, b->tune, b->n_cu, false, s, clk));
+    FIZI_HIP(hipEventRecord(b->cls_ev[par], s));
+    FIZI_HIP(hipStreamWaitEvent(b->side, b->cls_ev[par], 0));
+    FIZI_TRY(run_back(b->ring.d[slot], T, njobs, b->n, b->max_wd, b->max_ops, b->tune, b->n_cu, false, b->side,
+                      clk, true));
+    FIZI_HIP(hipEventRecord(b->join_ev[par], b->side));
+    FIZI_TRY(b->ring.finish(slot, b->side));
+    if (b->pend_join >= 0)
+        FIZI_HIP(hipStreamWaitEvent(s, b->join_ev[b->pend_join], 0));
+    b->pend_join = par;
+    return FIZI_OK;
+}
+
+// Graph of a pipelined step (slot, pending slot or -1), captured once: the
+// capture forks onto the side stream and joins back.
+int pgraph_for(fizi_batch *b, int slot, int pend)
+{
+    hipGraphExec_t &ge = b->pgraph[slot][pend + 1];
+    if (ge)
+        return FIZI_OK;
+    if (!b->cap)
+        FIZI_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    FIZI_TRY(side_streams(b));
+    FIZI_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+    const int rc = enqueue_pipelined(b, slot, b->n, pend, b->n, true, b->cap, b->side, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc != FIZI_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return rc;
+    }
+    FIZI_HIP(e);
+    const hipError_t e2 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    FIZI_HIP(e2);
+    return FIZI_OK;
+}
+
+// Makes every step's outputs complete on s: enqueues the graph form's
+// pending back half there, or joins the direct form's side stream.
+int flush_pending(fizi_batch *b, hipStream_t s)
+{
+    if (b->pend_slot < 0 && b->pend_join < 0)
+        return FIZI_OK;
+    FIZI_TRY(order_after_previous(b, s));
+    if (b->pend_slot >= 0) {
+        const int p = b->pend_slot;
+        FIZI_TRY(run_back(b->ring.d[p], *b->ring.h[p], b->pend_jobs, b->n, b->max_wd, b->max_ops, b->tune,
+                          b->n_cu, false, s, &b->clk));
+        b->pend_slot = -1;
+        FIZI_TRY(b->ring.finish(p, s));
+    }
+    if (b->pend_join >= 0) {
+        FIZI_HIP(hipStreamWaitEvent(s, b->join_ev[b->pend_join], 0));
+        b->pend_join = -1;
+    }
+    return mark_last(b, s);
+}
+
+// Flushes on the stream of the last call and waits for all of the batch's work.
+int drain(fizi_batch *b)
+{
+    if (b->pend_slot >= 0 || b->pend_join >= 0)
+        FIZI_TRY(flush_pending(b, b->last_stream));
+    if (b->have_last)
+        FIZI_HIP(hipEventSynchronize(b->order_ev));
+    return FIZI_OK;
+}
+
 // Graph of one table slot: upload + pipeline, captured once.
 int graph_for(fizi_batch *b, int slot)
 {
@@ -126,11 +268,17 @@ int graph_for(fizi_batch *b, int slot)
 
 void drop_graphs(fizi_batch *b)
 {
-    for (int i = 0; i < kTabSlots; ++i)
+    for (int i = 0; i < kTabSlots; ++i) {
         if (b->graph[i]) {
             (void)hipGraphExecDestroy(b->graph[i]);
             b->graph[i] = nullptr;
         }
+        for (int p = 0; p <= kTabSlots; ++p)
+            if (b->pgraph[i][p]) {
+                (void)hipGraphExecDestroy(b->pgraph[i][p]);
+                b->pgraph[i][p] = nullptr;
+            }
+    }
 }
 
 }  // namespace
@@ -164,10 +312,12 @@ int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_para
     b->slot.resize(n_streams);
     b->frames.assign(n_streams, 0);
     b->epoch.assign(n_streams, 0);
+    b->raw2.resize(n_streams);
     int max_w = 0;
     for (int i = 0; i < n_streams; ++i) {
         model_at(b->m[i], geoms[i], params[i], b->d + L.model[i]);
         b->slot[i] = slot_at(geoms[i], b->d + L.slot[i]);
+        b->raw2[i] = reinterpret_cast<uint64_t *>(b->d + L.raw2[i]);
         max_w = std::max(max_w, geoms[i].width);
         b->max_ops = std::max(b->max_ops, morph_ops(params[i]));
     }
@@ -179,6 +329,15 @@ int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_para
         rc = b->ring.init(b->d + L.tables);
     if (rc == FIZI_OK) {
         hipError_t e = hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            e = hipEventCreateWithFlags(&b->up_ev[k], hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&b->cls_ev[k], hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&b->join_ev[k], hipEventDisableTiming);
+        }
         if (e == hipSuccess)
             e = (hipError_t)launch_fill_u32(reinterpret_cast<uint32_t *>(b->persist), 0u,
                                              persist_state_bytes() / 4, nullptr);
@@ -214,6 +373,7 @@ int fizi_batch_learn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames, 
     if (!reset && !m.learned)
         return fail(FIZI_ESTATE, "learning without reset needs a learned model");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    FIZI_TRY(flush_pending(b, s));
     FIZI_TRY(order_after_previous(b, s));
     FIZI_TRY(learn_model(m, b->ring, b->tune, b->n_cu, d_frames, n_frames, reset, s, &b->clk));
     return mark_last(b, s);
@@ -234,6 +394,7 @@ int fizi_batch_relearn(fizi_batch *b, int32_t stream_id, const uint8_t *d_frames
     if (!m.learned)
         return fail(FIZI_ESTATE, "relearning needs a learned model");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    FIZI_TRY(flush_pending(b, s));
     FIZI_TRY(order_after_previous(b, s));
     FIZI_TRY(learn_model(m, b->ring, b->tune, b->n_cu, d_frames, n_frames, 0, s, &b->clk, d_fizi_bits));
     return mark_last(b, s);
@@ -245,8 +406,7 @@ int fizi_batch_set_tracking(fizi_batch *b, int32_t stream_id, int32_t enable)
         return fail(FIZI_EINVAL, "null batch");
     if (stream_id < 0 || stream_id >= b->n)
         return fail(FIZI_EINVAL, "stream_id out of range");
-    if (b->have_last)
-        FIZI_HIP(hipEventSynchronize(b->order_ev));
+    FIZI_TRY(drain(b));
     Model &m = b->m[stream_id];
     FIZI_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(m.track), 0u, sizeof(TrackState) / 4, nullptr));
     FIZI_HIP(hipStreamSynchronize(nullptr));
@@ -258,13 +418,10 @@ int fizi_batch_set_mode(fizi_batch *b, int32_t mode)
 {
     if (!b)
         return fail(FIZI_EINVAL, "null batch");
-    if (mode < FIZI_BATCH_DIRECT || mode > FIZI_BATCH_PERSISTENT_GRAPH)
+    if (mode < FIZI_BATCH_DIRECT || mode > FIZI_BATCH_PIPELINED_GRAPH)
         return fail(FIZI_EINVAL, "unknown batch mode");
-    if (b->have_last)
-        FIZI_HIP(hipEventSynchronize(b->order_ev));
-    const bool persistent = mode == FIZI_BATCH_PERSISTENT || mode == FIZI_BATCH_PERSISTENT_GRAPH;
-    const bool old_persistent = b->mode == FIZI_BATCH_PERSISTENT || b->mode == FIZI_BATCH_PERSISTENT_GRAPH;
-    if (persistent != old_persistent)
+    FIZI_TRY(drain(b));
+    if (is_persistent(mode) != is_persistent(b->mode))
         drop_graphs(b);
     b->mode = mode;
     return FIZI_OK;
@@ -286,6 +443,7 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
     int slot;
     FIZI_TRY(b->ring.take(&slot));
     Table &T = *b->ring.h[slot];
+    const bool pipelined = is_pipelined(b->mode);
     int k = 0;
     for (int i = 0; i < b->n; ++i) {
         if (!h_frames[i])
@@ -293,6 +451,8 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
         Job &J = T.jobs[k++];
         fill_job(b->m[i], b->tune.morph_rows, J);
         set_scratch(J, b->slot[i]);
+        if (pipelined && b->parity)
+            J.raw = b->raw2[i];
         J.frame = h_frames[i];
         if (h_fizi_bits && h_fizi_bits[i])
             J.fizi = h_fizi_bits[i];
@@ -303,6 +463,29 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
         J.epoch = b->epoch[i];
     }
     set_prefixes(T, k, b->tune);
+    if (pipelined) {
+        if (k == 0) {
+            FIZI_TRY(b->ring.finish(slot, s));
+            return mark_last(b, s);
+        }
+        if (b->mode == FIZI_BATCH_PIPELINED) {
+            FIZI_TRY(enqueue_pipelined_direct(b, slot, k, s, &b->clk));
+            b->parity ^= 1;
+            return mark_last(b, s);
+        }
+        const int pend = b->pend_slot;
+        FIZI_TRY(pgraph_for(b, slot, pend));
+        FIZI_HIP(hipGraphLaunch(b->pgraph[slot][pend + 1], s));
+        b->parity ^= 1;
+        // the pending step's table was read until the join: its slot is
+        // reusable after this call
+        if (pend >= 0)
+            FIZI_TRY(b->ring.finish(pend, s));
+        b->pend_slot = slot;
+        b->pend_jobs = k;
+        FIZI_TRY(b->ring.finish(slot, s));
+        return mark_last(b, s);
+    }
     const bool graphed = b->mode == FIZI_BATCH_GRAPH || b->mode == FIZI_BATCH_PERSISTENT_GRAPH;
     if (k > 0) {
         if (graphed) {
@@ -318,6 +501,13 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
     }
     FIZI_TRY(b->ring.finish(slot, s));
     return mark_last(b, s);
+}
+
+int fizi_batch_flush(fizi_batch *b, void *stream)
+{
+    if (!b)
+        return fail(FIZI_EINVAL, "null batch");
+    return flush_pending(b, static_cast<hipStream_t>(stream));
 }
 
 int fizi_batch_get_tuning(fizi_batch *b, fizi_tuning *out)
@@ -341,10 +531,9 @@ int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t)
         return fail(FIZI_EINVAL, "morph_rows must be 8, 16, 32 or 64");
     if (t->grid_per_cu < 1 || t->grid_per_cu > 64)
         return fail(FIZI_EINVAL, "grid_per_cu must be in [1, 64]");
-    if (t->mode < FIZI_BATCH_DIRECT || t->mode > FIZI_BATCH_PERSISTENT_GRAPH)
+    if (t->mode < FIZI_BATCH_DIRECT || t->mode > FIZI_BATCH_PIPELINED_GRAPH)
         return fail(FIZI_EINVAL, "unknown batch mode");
-    if (b->have_last)
-        FIZI_HIP(hipEventSynchronize(b->order_ev));
+    FIZI_TRY(drain(b));
     drop_graphs(b);
     b->tune.cls_iters = t->cls_iters;
     b->tune.morph_rows = t->morph_rows;
@@ -374,6 +563,7 @@ int fizi_batch_autotune(fizi_batch *b, const uint8_t *const *h_frames, fizi_poin
         FIZI_HIP(hipEventRecord(e0, s));
         for (int i = 0; i < steps; ++i)
             FIZI_TRY(fizi_batch_step(b, h_frames, nullptr, d_pointers, stream));
+        FIZI_TRY(fizi_batch_flush(b, stream));
         FIZI_HIP(hipEventRecord(e1, s));
         FIZI_HIP(hipEventSynchronize(e1));
         float el = 0.f;
@@ -407,7 +597,8 @@ int fizi_batch_autotune(fizi_batch *b, const uint8_t *const *h_frames, fizi_poin
         return FIZI_OK;
     };
     if (rc == FIZI_OK)
-        rc = sweep(&fizi_tuning::mode, {FIZI_BATCH_GRAPH, FIZI_BATCH_PERSISTENT_GRAPH});
+        rc = sweep(&fizi_tuning::mode, {FIZI_BATCH_GRAPH, FIZI_BATCH_PERSISTENT_GRAPH, FIZI_BATCH_PIPELINED,
+                                        FIZI_BATCH_PIPELINED_GRAPH});
     if (rc == FIZI_OK)
         rc = sweep(&fizi_tuning::cls_iters, {2, 4, 8});
     if (rc == FIZI_OK)
@@ -429,8 +620,7 @@ int fizi_batch_status(fizi_batch *b, uint32_t *h_flags)
 {
     if (!b || !h_flags)
         return fail(FIZI_EINVAL, "null argument");
-    if (b->have_last)
-        FIZI_HIP(hipEventSynchronize(b->order_ev));
+    FIZI_TRY(drain(b));
     uint32_t *err = &reinterpret_cast<PersistState *>(b->persist)->error;
     FIZI_HIP(hipMemcpy(h_flags, err, sizeof(uint32_t), hipMemcpyDeviceToHost));
     if (*h_flags) {
@@ -471,15 +661,22 @@ int fizi_batch_destroy(fizi_batch *b)
 {
     if (!b)
         return FIZI_OK;
+    // a pending half-step is dropped (its buffers may be gone by now)
     if (b->have_last)
         (void)hipEventSynchronize(b->order_ev);
     drop_graphs(b);
     if (b->cap)
         (void)hipStreamDestroy(b->cap);
+    if (b->side)
+        (void)hipStreamDestroy(b->side);
+    if (b->up)
+        (void)hipStreamDestroy(b->up);
     b->ring.destroy();
     b->clk.destroy();
-    if (b->order_ev)
-        (void)hipEventDestroy(b->order_ev);
+    for (hipEvent_t e : {b->order_ev, b->fork_ev, b->up_ev[0], b->up_ev[1], b->cls_ev[0], b->cls_ev[1],
+                         b->join_ev[0], b->join_ev[1]})
+        if (e)
+            (void)hipEventDestroy(e);
     delete b;
     return FIZI_OK;
 }

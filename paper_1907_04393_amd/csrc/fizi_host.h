@@ -121,5 +121,13 @@ int learn_model(Model &m, TableRing &ring, const Tuning &t, int n_cu, const uint
 // the number of jobs (for graph capture); max_jobs bounds the resolve grid.
 int run_pipeline(const Table *d_tab, const Table &h, int njobs, int max_jobs, int max_wd, int max_ops,
                  const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk);
+// Its two halves: gain and classify (the front, which reads the frames and
+// writes the raw bits), then morphology and components (the back, which
+// reads the raw bits and writes I_FIZI and the pointers). beside: the back
+// half runs beside another step's front (smaller component workgroups).
+int run_front(const Table *d_tab, const Table &h, int njobs, const Tuning &t, int n_cu, bool fixed_grid,
+              hipStream_t s, StageClock *clk);
+int run_back(const Table *d_tab, const Table &h, int njobs, int max_jobs, int max_wd, int max_ops,
+             const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk, bool beside = false);
 
 }  // namespace fizi

@@ -386,20 +386,35 @@ int learn_model(Model &m, TableRing &ring, const Tuning &t, int n_cu, const uint
     return FIZI_OK;
 }
 
-int run_pipeline(const Table *d_tab, const Table &h, int njobs, int max_jobs, int max_wd, int max_ops,
-                 const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk)
+int run_front(const Table *d_tab, const Table &h, int njobs, const Tuning &t, int n_cu, bool fixed_grid,
+              hipStream_t s, StageClock *clk)
 {
     auto ev = [&](int st) { return clk ? clk->next(st) : StageEvents{}; };
     const int big = INT_MAX / 2;
     FIZI_HIP(launch_gain(d_tab, fixed_grid ? big : h.h.gain_pre[njobs], n_cu, t, s, ev(FIZI_STAGE_GAIN)));
     FIZI_HIP(launch_classify(d_tab, fixed_grid ? big : h.h.cls_pre[njobs], n_cu, t, s,
                              ev(FIZI_STAGE_CLASSIFY)));
+    return FIZI_OK;
+}
+
+int run_back(const Table *d_tab, const Table &h, int njobs, int max_jobs, int max_wd, int max_ops,
+             const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk, bool beside)
+{
+    auto ev = [&](int st) { return clk ? clk->next(st) : StageEvents{}; };
+    const int big = INT_MAX / 2;
     FIZI_HIP(launch_morph(d_tab, fixed_grid ? big : h.h.mor_pre[njobs], max_wd, max_ops, n_cu, t, s,
                           ev(FIZI_STAGE_MORPH)));
     // tracked consecutive frames of one stream are resolved in order
     const bool serial = njobs > 1 && h.jobs[0].track != nullptr && h.jobs[1].track == h.jobs[0].track;
-    FIZI_HIP(launch_resolve(d_tab, fixed_grid ? max_jobs : njobs, s, ev(FIZI_STAGE_RESOLVE), serial));
+    FIZI_HIP(launch_resolve(d_tab, fixed_grid ? max_jobs : njobs, s, ev(FIZI_STAGE_RESOLVE), serial, beside));
     return FIZI_OK;
+}
+
+int run_pipeline(const Table *d_tab, const Table &h, int njobs, int max_jobs, int max_wd, int max_ops,
+                 const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk)
+{
+    FIZI_TRY(run_front(d_tab, h, njobs, t, n_cu, fixed_grid, s, clk));
+    return run_back(d_tab, h, njobs, max_jobs, max_wd, max_ops, t, n_cu, fixed_grid, s, clk);
 }
 
 }  // namespace fizi

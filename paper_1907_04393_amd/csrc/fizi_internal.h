@@ -151,8 +151,10 @@ hipError_t launch_classify(const Table *d_tab, int total_tiles, int n_cu, const 
 hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max_ops, int n_cu,
                         const Tuning &t, hipStream_t s, StageEvents ev = {});
 // serial: one workgroup takes the jobs in table order (consecutive frames of
-// one tracked stream).
-hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev = {}, bool serial = false);
+// one tracked stream); small: 256-thread workgroups, for a launch that runs
+// beside a streaming kernel.
+hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev = {}, bool serial = false,
+                          bool small = false);
 hipError_t launch_persistent(const Table *d_tab, int max_wd, int max_ops, int n_cu, const Tuning &t,
                              uint8_t *persist, hipStream_t s, StageEvents ev = {});
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);

@@ -1413,7 +1413,12 @@ __global__ __launch_bounds__(256) void k_morph(Table *__restrict__ T)
 }
 
 // ---------------------------------------------------------------------------
+// Workgroup of the component stage: 1024 threads when it runs on its own;
+// 256 when it runs beside a streaming kernel (pipelined steps), where a
+// 1024-thread workgroup, four waves on every SIMD of a CU, finds no room
+// until the streaming kernel drains.
 constexpr int kResolveThreads = 1024;
+constexpr int kResolveThreadsSmall = 256;
 constexpr int kMaxWaves = 16;
 
 // Component areas of one frame, summed in LDS: an open-addressing table from
@@ -1688,7 +1693,8 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kResolveThreads) void k_resolve(Table *__restrict__ T)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_resolve(Table *__restrict__ T)
 {
     __shared__ AreaTable s_tab;
     const int nj = T->h.njobs;
@@ -1921,11 +1927,16 @@ hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev, bool serial)
+hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev, bool serial, bool small)
 {
     if (njobs <= 0)
         return hipSuccess;
-    FIZI_LAUNCH(k_resolve, serial ? 1 : njobs, kResolveThreads, 0, s, ev, const_cast<Table *>(d_tab));
+    if (small)
+        FIZI_LAUNCH(k_resolve<kResolveThreadsSmall>, serial ? 1 : njobs, kResolveThreadsSmall, 0, s, ev,
+                    const_cast<Table *>(d_tab));
+    else
+        FIZI_LAUNCH(k_resolve<kResolveThreads>, serial ? 1 : njobs, kResolveThreads, 0, s, ev,
+                    const_cast<Table *>(d_tab));
     return hipGetLastError();
 }
 

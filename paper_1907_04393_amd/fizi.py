@@ -127,6 +127,7 @@ def _extra_signatures(L):
         L.fizi_batch_set_tracking.argtypes = [vp, i32, i32]
         L.fizi_batch_step.argtypes = [vp, P(vp), P(vp), vp, vp]
         L.fizi_batch_set_mode.argtypes = [vp, i32]
+        L.fizi_batch_flush.argtypes = [vp, vp]
         L.fizi_batch_status.argtypes = [vp, P(ctypes.c_uint32)]
         L.fizi_batch_state_layout.argtypes = [vp, i32, P(Layout)]
         L.fizi_batch_stage_timing.argtypes = [vp, i32]
@@ -170,6 +171,15 @@ def state_bytes(width, height, params=None, chunk=16) -> int:
     return int(lib().fizi_state_bytes(ctypes.byref(Geom(width, height)), ctypes.byref(params), chunk))
 
 
+def _device(device) -> torch.device:
+    """A CUDA device with its index ("cuda" is the current device), so that it
+    compares equal to the device of the tensors allocated on it."""
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
@@ -202,7 +212,7 @@ class Context:
         if nbytes == 0:
             check(L.fizi_validate(ctypes.byref(self.geom), ctypes.byref(self.params)))
             raise FiziError(FIZI_EINVAL, "chunk must be in [1, 256]")
-        self.device = torch.device(device)
+        self.device = _device(device)
         self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._h = ctypes.c_void_p()
         check(L.fizi_create(ctypes.byref(self.geom), ctypes.byref(self.params), self.chunk,
@@ -305,6 +315,9 @@ class Context:
 
 
 BATCH_DIRECT, BATCH_GRAPH, BATCH_PERSISTENT, BATCH_PERSISTENT_GRAPH = 0, 1, 2, 3
+# software-pipelined across steps: a step's outputs are written by the next
+# step or by flush()
+BATCH_PIPELINED, BATCH_PIPELINED_GRAPH = 4, 5
 
 
 class Batch:
@@ -322,12 +335,15 @@ class Batch:
         nbytes = int(L.fizi_batch_state_bytes(self.n, self._g, self._p))
         if nbytes == 0:
             raise FiziError(FIZI_EINVAL, "invalid stream geometry or parameters")
-        self.device = torch.device(device)
+        self.device = _device(device)
         self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._h = ctypes.c_void_p()
         check(L.fizi_batch_create(self.n, self._g, self._p, _ptr(self.state), nbytes, ctypes.byref(self._h)))
         self._frames = (ctypes.c_void_p * self.n)()
         self._fizi = (ctypes.c_void_p * self.n)()
+        # the last step's output tensors: in the pipelined modes they are
+        # written by the next step or flush(), so they are kept alive until then
+        self._held = None
 
     @staticmethod
     def stream_bytes(geom, params=None) -> int:
@@ -411,6 +427,13 @@ class Batch:
                 self._fizi[i] = f.data_ptr() if f is not None else None
             fz = self._fizi
         check(lib().fizi_batch_step(self._h, fr, fz, _ptr(pointers), _stream(stream)))
+        self._held = (pointers, None if fizi is None else list(fizi))
+
+    def flush(self, stream=None):
+        """Enqueues the pending half-step of the pipelined modes (after it
+        completes on the stream, every step's outputs are written)."""
+        check(lib().fizi_batch_flush(self._h, _stream(stream)))
+        self._held = None
 
     def get_tuning(self) -> dict:
         t = Tuning()

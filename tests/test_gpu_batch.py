@@ -1,6 +1,9 @@
 """GPU parity of the batched form: every stream's I_FIZI and pointer equal
 the CPU oracle's, in every launch mode (direct kernels, hipGraph replay,
-persistent fused kernel, persistent kernel from a hipGraph)."""
+persistent fused kernel, persistent kernel from a hipGraph, and the
+software-pipelined steps, direct and from hipGraphs). Steps write into fresh
+output buffers and are read after a flush, so that the pipelined modes (whose
+outputs the next step writes) are checked the same way."""
 import numpy as np
 import pytest
 import torch
@@ -9,7 +12,7 @@ from helpers import need_gpu
 
 pytestmark = pytest.mark.gpu
 
-MODES = (0, 1, 2, 3)
+MODES = (0, 1, 2, 3, 4, 5)
 
 
 def _streams():
@@ -56,14 +59,19 @@ def test_batch_matches_oracle(mode):
     for i, (bg, _) in enumerate(data):
         b.learn(i, bg.to(dev))
     hands = [h.to(dev) for _, h in data]
-    fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in specs]
     orc = _oracle(specs, params, data)
     counts = [0] * len(specs)
+    outs = []
     for k, act in enumerate(ACTIVE):
         ptrs = torch.full((len(specs), 56), 0xAB, dtype=torch.uint8, device=dev)
+        fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in specs]
         frames = [hands[i][k] if act[i] else None for i in range(len(specs))]
         b.step(frames, ptrs, fizi=fz)
-        torch.cuda.synchronize()
+        outs.append((ptrs, fz))
+    b.flush()
+    torch.cuda.synchronize()
+    for k, act in enumerate(ACTIVE):
+        ptrs, fz = outs[k]
         got = fizi.pointers_to_numpy(ptrs)
         raw = ptrs.cpu().numpy()
         for i, sp in enumerate(specs):
@@ -159,12 +167,15 @@ def test_batched_workload_full_size():
 
 def _run_steps(b, hands, specs, nsteps, dev):
     from paper_1907_04393_amd import fizi
-    outs = []
+    bufs, outs = [], []
     for k in range(nsteps):
         ptrs = torch.empty((len(specs), 56), dtype=torch.uint8, device=dev)
         fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in specs]
         b.step([h[k] for h in hands], ptrs, fizi=fz)
-        torch.cuda.synchronize()
+        bufs.append((ptrs, fz))
+    b.flush()
+    torch.cuda.synchronize()
+    for ptrs, fz in bufs:
         ps = [fizi.pointer_dict(p) for p in fizi.pointers_to_numpy(ptrs)]
         for p in ps:
             p.pop("frame_index")
@@ -191,7 +202,7 @@ def test_every_launch_shape_gives_the_same_result():
     b.set_tuning(mode=0, cls_iters=4, morph_rows=32, grid_per_cu=8)
     ref = _run_steps(b, hands, specs, 2, dev)
     shapes = [dict(mode=m, cls_iters=c, morph_rows=r, grid_per_cu=g)
-              for m in (0, 1, 2, 3) for c in (2, 8) for r in (8, 64) for g in ((1, 16) if m == 0 else (8,))]
+              for m in MODES for c in (2, 8) for r in (8, 64) for g in ((1, 16) if m in (0, 4) else (8,))]
     shapes += [dict(mode=0, cls_iters=1, morph_rows=16, grid_per_cu=4)]
     for sh in shapes:
         print("shape", sh, flush=True)
@@ -238,15 +249,19 @@ def test_dense_masks_every_band_height():
     for i, (bg, _) in enumerate(data):
         b.learn(i, bg.to(dev))
     hands = [h.to(dev) for _, h in data]
-    for mode in (0, 2):
+    for mode in (0, 2, 4):
         for rows in (8, 16, 32, 64):
             print("dense batch mode", mode, "rows", rows, flush=True)
             b.set_tuning(mode=mode, cls_iters=4, morph_rows=rows, grid_per_cu=8)
+            bufs = []
             for k in range(2):
                 ptrs = torch.empty((len(cases), 56), dtype=torch.uint8, device=dev)
                 fz = [torch.empty((H, W // 64), dtype=torch.int64, device=dev) for W, H, _ in cases]
                 b.step([h[k] for h in hands], ptrs, fizi=fz)
-                torch.cuda.synchronize()
+                bufs.append((ptrs, fz))
+            b.flush()
+            torch.cuda.synchronize()
+            for k, (ptrs, fz) in enumerate(bufs):
                 got = fizi.pointers_to_numpy(ptrs)
                 for i, (W, H, kind) in enumerate(cases):
                     p = fizi.pointer_dict(got[i])
@@ -279,15 +294,33 @@ def test_batch_wide_and_narrow_streams(mode):
         m.learn(bg.numpy())
         data.append(hand)
         orc.append(m)
-    fz = [torch.empty((H, W // 64), dtype=torch.int64, device=dev) for W, H in shapes]
+    dev_frames = [h.to(dev) for h in data]
+    bufs = []
     for k in range(3):
         ptrs = torch.empty((len(shapes), 56), dtype=torch.uint8, device=dev)
-        b.step([h[k].to(dev) for h in data], ptrs, fizi=fz)
-        torch.cuda.synchronize()
+        fz = [torch.empty((H, W // 64), dtype=torch.int64, device=dev) for W, H in shapes]
+        b.step([h[k] for h in dev_frames], ptrs, fizi=fz)
+        bufs.append((ptrs, fz))
+    b.flush()
+    torch.cuda.synchronize()
+    for k, (ptrs, fz) in enumerate(bufs):
         got = fizi.pointers_to_numpy(ptrs)
         for i, (W, H) in enumerate(shapes):
             ref = orc[i].process(data[i][k].numpy(), frame_index=k)
             assert fizi.pointer_dict(got[i]) == ref["pointer"], (mode, k, i)
             assert np.array_equal(fizi.unpack_bits(fz[i], W), ref["fizi"]), (mode, k, i)
     assert b.status() == 0
+    b.close()
+
+
+def test_default_cuda_device_accepts_indexed_frames():
+    """A batch made on "cuda" takes frames allocated on "cuda:0"."""
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    b = fizi.Batch([(64, 8)], device="cuda")
+    b.learn(0, torch.full((1, 8, 64, 3), 50, dtype=torch.uint8, device=dev))
+    ptrs = torch.zeros((1, 56), dtype=torch.uint8, device=dev)
+    b.step([torch.full((8, 64, 3), 50, dtype=torch.uint8, device=dev)], ptrs)
+    torch.cuda.synchronize()
+    assert fizi.pointer_dict(fizi.pointers_to_numpy(ptrs)[0])["present"] == 0
     b.close()

@@ -54,7 +54,7 @@ def test_forced_gain_at_the_bounds(inv, delta, S):
     assert differs == (inv != 65536)
 
 
-@pytest.mark.parametrize("mode", (0, 1, 2, 3))
+@pytest.mark.parametrize("mode", (0, 1, 2, 3, 4, 5))
 def test_batch_mixes_both_options(mode):
     from oracle import oracle
     from paper_1907_04393_amd import fizi, scene
@@ -77,11 +77,16 @@ def test_batch_mixes_both_options(mode):
         m.learn(bg.numpy())
         data.append(hand)
         orc.append(m)
-    fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in specs]
+    dev_frames = [h.to(dev) for h in data]
+    bufs = []
     for k in range(4):
         ptrs = torch.empty((len(specs), 56), dtype=torch.uint8, device=dev)
-        b.step([h[k].to(dev) for h in data], ptrs, fizi=fz)
-        torch.cuda.synchronize()
+        fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in specs]
+        b.step([h[k] for h in dev_frames], ptrs, fizi=fz)
+        bufs.append((ptrs, fz))
+    b.flush()
+    torch.cuda.synchronize()
+    for k, (ptrs, fz) in enumerate(bufs):
         got = fizi.pointers_to_numpy(ptrs)
         for i, sp in enumerate(specs):
             ref = orc[i].process(data[i][k].numpy(), frame_index=k)

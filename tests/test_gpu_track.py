@@ -115,7 +115,7 @@ def test_scene_tracking_matches_oracle():
         assert np.array_equal(hd[k], ref[k]["hand"]), k
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5])
 def test_batch_tracking_matches_oracle(mode):
     from oracle import oracle
     from paper_1907_04393_amd import fizi
@@ -132,10 +132,13 @@ def test_batch_tracking_matches_oracle(mode):
     mb = oracle.Model(192, 70)
     mb.learn(bgb.numpy())
     fa, fb = fr.to(dev), frb.to(dev)
+    bufs = []
     for k in range(fr.shape[0]):
-        ptrs = torch.empty((2, 56), dtype=torch.uint8, device=dev)
-        b.step([fa[k], fb[k]], ptrs)
-        torch.cuda.synchronize()
+        bufs.append(torch.empty((2, 56), dtype=torch.uint8, device=dev))
+        b.step([fa[k], fb[k]], bufs[-1])
+    b.flush()
+    torch.cuda.synchronize()
+    for k, ptrs in enumerate(bufs):
         got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(ptrs)]
         assert got[0] == ref_a[k]["pointer"], (mode, k)
         assert got[1] == mb.process(frb[k].numpy(), frame_index=k)["pointer"], (mode, k)
@@ -191,7 +194,7 @@ def test_plain_click_debounce_matches_oracle(D, chunk):
     assert [int(r["click"]) for r in fizi.pointers_to_numpy(out["pointers"])] == [int(s == "F") for s in SHAPES]
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5])
 def test_batch_click_debounce_matches_oracle(mode):
     from oracle import oracle
     from paper_1907_04393_amd import fizi
@@ -210,10 +213,13 @@ def test_batch_click_debounce_matches_oracle(mode):
     mb = oracle.Model(192, 70, oracle.params(click_debounce=3))
     mb.learn(bgb.numpy())
     fa, fb = fr.to(dev), frb.to(dev)
+    bufs = []
     for k in range(len(SHAPES)):
-        ptrs = torch.empty((2, 56), dtype=torch.uint8, device=dev)
-        b.step([fa[k], fb[k]], ptrs)
-        torch.cuda.synchronize()
+        bufs.append(torch.empty((2, 56), dtype=torch.uint8, device=dev))
+        b.step([fa[k], fb[k]], bufs[-1])
+    b.flush()
+    torch.cuda.synchronize()
+    for k, ptrs in enumerate(bufs):
         got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(ptrs)]
         assert got[0] == ref_a[k]["pointer"], (mode, k)
         # stream 1 is not tracked: its clicks are the frame's own
