@@ -367,6 +367,23 @@ int fizi_soft_backward(const uint8_t *d_frames, const float *d_dLdm, int64_t npx
 int fizi_soft_bce(const uint8_t *d_frames, const uint8_t *d_gt, int64_t npx, const float params6[6],
                   float T, void *d_workspace, size_t workspace_bytes, double *d_out7, void *stream);
 
+/* For callers that cannot allocate device memory (work under hipGraph
+ * capture, serving loops or harnesses that forbid hipMalloc): fizi_soft_bce
+ * without a workspace argument. Its per-block partial sums go to a
+ * 128 KiB array the library holds on each GPU (a static device array, kept
+ * until the process ends); the call allocates nothing (no hipMalloc, no
+ * library allocation). The array holds one row of 8 partial sums for each
+ * of the at most 2048 blocks a launch uses, whatever npx is; a launch that
+ * would need more is refused with FIZI_ENOMEM. Same arguments, results (bit
+ * for bit) and errors as fizi_soft_bce otherwise. Every call on one GPU uses
+ * the same array and it keeps the last call's contents (each block writes
+ * its row before the final sum reads it, so nothing needs clearing): calls
+ * that overlap on a GPU (on different streams, or from several threads
+ * without ordering) race and give undefined results; order them on one
+ * stream. Async. */
+int fizi_soft_bce_static(const uint8_t *d_frames, const uint8_t *d_gt, int64_t npx, const float params6[6],
+                         float T, double *d_out7, void *stream);
+
 /* ---- The pointer's consumers (host) ---------------------------------------
  * A pointer's position is its centroid pixel (floor(sum_x / area),
  * floor(sum_y / area)); a frame without a hand has none. */

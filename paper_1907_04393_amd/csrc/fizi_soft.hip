@@ -4,6 +4,7 @@
 // [[s_bb, s_br], [s_br, s_rr]]. Per-pixel arithmetic in FP32; gradient and
 // loss sums in FP64, reduced in a fixed order (bitwise reproducible).
 #include <cmath>
+#include <mutex>
 
 #include "fizi_host.h"
 
@@ -294,6 +295,45 @@ int soft_backward(const uint8_t *frames, const float *dLdm, const uint8_t *gt, l
 }  // namespace
 }  // namespace fizi
 
+// Partial sums of the allocation-free BCE entry point: one row of 8 doubles
+// per block of the backward kernel, for as many blocks as a launch ever
+// uses (128 KiB). Every GPU the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress gives on each device.
+static __device__ __align__(256) double scratch[2048 * 8];
+
+namespace fizi {
+namespace {
+
+static_assert(sizeof(scratch) == (size_t)kSoftBlocksMax * kSoftOut * sizeof(double),
+              "one row of partial sums per block of the largest launch");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+int scratch_of_current_device(double **out)
+{
+    int dev = 0;
+    FIZI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(FIZI_EINVAL, "device ordinal beyond the library's table of 64 devices");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        FIZI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p)
+            return fail(FIZI_EHIP, "hipGetSymbolAddress gave no address for the scratch array");
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return FIZI_OK;
+}
+
+}  // namespace
+}  // namespace fizi
+
 using namespace fizi;
 
 extern "C" {
@@ -337,6 +377,20 @@ int fizi_soft_bce(const uint8_t *d_frames, const uint8_t *d_gt, int64_t npx, con
         return fail(FIZI_EINVAL, "null ground truth");
     return soft_backward(d_frames, nullptr, d_gt, npx, params6, T, d_workspace, workspace_bytes, d_out7, 7,
                          stream);
+}
+
+int fizi_soft_bce_static(const uint8_t *d_frames, const uint8_t *d_gt, int64_t npx, const float params6[6],
+                         float T, double *d_out7, void *stream)
+{
+    if (!d_gt)
+        return fail(FIZI_EINVAL, "null ground truth");
+    if (npx >= 1 && (size_t)soft_grid(npx) * kSoftOut * sizeof(double) > sizeof(scratch))
+        return fail(FIZI_ENOMEM, "the launch needs more partial sums than the 128 KiB static array holds");
+    double *ws = nullptr;
+    FIZI_TRY(scratch_of_current_device(&ws));
+    // every block writes its whole row of partial sums before the final sum
+    // reads it: nothing in the array has to start at zero
+    return soft_backward(d_frames, nullptr, d_gt, npx, params6, T, ws, sizeof(scratch), d_out7, 7, stream);
 }
 
 }  // extern "C"

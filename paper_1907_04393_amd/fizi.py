@@ -144,6 +144,7 @@ def _extra_signatures(L):
                                          ctypes.c_size_t, vp, vp]
         L.fizi_soft_bce.argtypes = [vp, vp, i64, P(ctypes.c_float), ctypes.c_float, vp,
                                     ctypes.c_size_t, vp, vp]
+        L.fizi_soft_bce_static.argtypes = [vp, vp, i64, P(ctypes.c_float), ctypes.c_float, vp, vp]
 
 
 def check(rc):

@@ -98,6 +98,22 @@ class _SoftBCE(torch.autograd.Function):
                                                                        dtype=params.dtype), None
 
 
+def soft_bce_static(frames, gt, params, T, out=None, stream=None):
+    """The fused loss and gradient through the allocation-free entry point
+    (its partial sums live in the library's static device array): returns
+    the 7 doubles (6 gradients, then the loss) in `out` (a device float64
+    tensor of 7, allocated here when not given)."""
+    _check_frames(frames)
+    npx = frames.numel() // 3
+    if gt.dtype != torch.uint8 or gt.numel() != npx or not gt.is_contiguous():
+        raise fizi.FiziError(fizi.FIZI_EINVAL, "gt must be a contiguous uint8 mask of one value per pixel")
+    if out is None:
+        out = torch.empty(7, dtype=torch.float64, device=frames.device)
+    fizi.check(fizi.lib().fizi_soft_bce_static(fizi._ptr(frames), fizi._ptr(gt), npx, _p6(params), float(T),
+                                               fizi._ptr(out), fizi._stream(stream)))
+    return out
+
+
 def soft_bce(frames, gt, params, T):
     """Mean BCE of the soft mask against gt, differentiable in params (one
     fused pass computes the loss and its gradient)."""
