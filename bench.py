@@ -5,18 +5,24 @@ Headline workload (batched form): 64 camera streams whose resolutions are
 drawn by seed from {640x480, 1280x720, 1920x1080, 3840x2160}, each with its
 own learned background, hand path and brightness drift. A step is one frame
 for every stream through the whole per-frame path (gain, classify,
-morphology, components, pointer): four kernels replayed from one hipGraph
-(with --autotune, the launch shape the batch's autotuner picks on these
-frames). Inputs are resident in HBM before the timed region.
+morphology, components, pointer). The launch shape (launch mode, classify
+tile, grid, band height) is the one the batch's autotuner picks on these
+frames during set-up. In the software-pipelined modes a step's morphology
+and components run beside the next step's classify; the timed region ends
+with a flush, so it holds exactly the timed steps' work. Inputs are resident
+in HBM before the timed region.
 
 Also measured, next to it: the plain single-stream form on 1920x1080 frames
 (throughput of process_frames over resident frames, and the latency of
-single-frame calls with the pointer read back on the host).
+single-frame calls with the pointer read back on the host), background
+learning, the soft mask, serving, and the CPU oracle on this host.
 
 Printed: one JSON line. `roofline` is the dominant kernel's (classify's, or
 the fused kernel's in a persistent launch shape) algorithmic bytes per launch
-over its average duration, taken from the kernel's own dispatch events;
-`cpu_baseline` is the CPU oracle on a bounded sample of the same frames.
+over its average duration, taken from the kernel's own dispatch events in
+the headline launch form; `traffic` is the HBM bytes rocprofv3 counted for
+that kernel's code (null when the built kernel differs from the one the
+counters were taken on); `cpu_baseline` is the CPU oracle on this host.
 """
 import argparse
 import json
@@ -32,18 +38,23 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per pixel of the whole per-frame path: frame 3 +
 # background min/max 6 + reference luminance 2/8 + I_FIZI bits 1/8
 PATH_BYTES_PER_PX = 9.375
-# of the classify kernel: frame 3 + background min/max 6 + raw mask bits 1/8
-CLASSIFY_BYTES_PER_PX = 9.125
-
+# of the classify kernel: frame 3 + background min/max 6 (its raw-mask
+# output is an intermediate, counted as overhead)
+CLASSIFY_BYTES_PER_PX = 9.0
 
 LAUNCH_NAMES = {0: "four kernels, direct launches", 1: "four kernels replayed from a hipGraph",
-                2: "persistent fused kernel", 3: "persistent fused kernel, hipGraph"}
+                2: "persistent fused kernel", 3: "persistent fused kernel, hipGraph",
+                4: "four kernels, pipelined across steps (back half on a side stream)",
+                5: "four kernels, pipelined across steps, hipGraphs"}
+# launch form whose kernels carry dispatch events: the same kernels in the
+# same order and streams as the mode timed (graph replays cannot carry them)
+TIMED_FORM = {0: 0, 1: 0, 2: 2, 3: 2, 4: 4, 5: 4}
 
-# measured HBM bytes per launch of the dominant kernel on this workload:
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB -> 1 GiB
-# elementwise kernel gives), keyed by kernel; valid only for the kernel code
-# the counters were taken on
-TRAFFIC = {"k_classify<4> (I_R1, I_R2, I_R3 per pixel)": 1714.1e6}
+# HBM bytes per launch of the dominant kernel on this workload, from
+# rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB -> 1 GiB
+# elementwise kernel gives), with the code hash of the kernel they were
+# taken on (the build writes lib/kernel_hashes.json)
+TRAFFIC = {"_ZN4fizi12_GLOBAL__N_110k_classifyILi4EEEvPNS_5TableE": ("6e994b625cb04815", 1714.1e6)}
 
 
 def log(*a):
@@ -55,6 +66,41 @@ def pct(a, q):
     return round(float(np.percentile(np.asarray(a), q)), 4)
 
 
+def kernel_hash(symbol):
+    try:
+        with open(os.path.join(ROOT, "paper_1907_04393_amd", "lib", "kernel_hashes.json")) as f:
+            return json.load(f).get(symbol)
+    except OSError:
+        return None
+
+
+def measured_traffic(symbol):
+    want = TRAFFIC.get(symbol)
+    if want is None or kernel_hash(symbol) != want[0]:
+        return None
+    return want[1]
+
+
+def copy_peak(torch):
+    """A plain device copy, 1 GiB read and 1 GiB written per launch, timed
+    with events: the bandwidth this machine's HBM gives a simple stream."""
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+    c = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(2):
+        c.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, c
+    return round(2 * (1 << 30) / sec / 1e9, 1)
+
+
 def bench_batched(args, torch, fizi, workloads):
     dev = torch.device("cuda:0")
     log("building the 64-stream workload")
@@ -64,57 +110,62 @@ def bench_batched(args, torch, fizi, workloads):
     stream = torch.cuda.current_stream()
 
     b.set_mode(workloads.BATCH_MODE)
-    if args.autotune:
-        best, ms = b.autotune(workloads.step_frames(w, 0), ptrs, steps=5, stream=stream)
+    autotuned = None
+    if not args.no_autotune:
+        best, ms = b.autotune(workloads.step_frames(w, 0), ptrs, steps=10, stream=stream)
+        autotuned = {"picked": best, "ms_per_step": round(ms, 4)}
         log(f"autotuned launch shape {best}: {ms:.3f} ms/step")
     tuning = b.get_tuning()
-    for k in range(args.warmup):
-        b.step(workloads.step_frames(w, k), ptrs, stream=stream)
+
+    def run(steps):
+        for k in range(steps):
+            b.step(workloads.step_frames(w, k), ptrs, stream=stream)
+        b.flush(stream=stream)
+
+    run(args.warmup)
     torch.cuda.synchronize()
     assert b.status() == 0
     log("warmup done; timed region")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        b.step(workloads.step_frames(w, k), ptrs, stream=stream)
+    run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     assert b.status() == 0
     sec = (t1 - t0) / args.steps
 
-    # per-step latency: submit a step, wait for its pointers on the host
+    # per-step latency: submit a step, make its outputs complete (flush),
+    # wait for its pointers on the host
     host = torch.empty((n, 56), dtype=torch.uint8, pin_memory=True)
     lat = []
     for k in range(args.latency_steps):
         t = time.perf_counter()
         b.step(workloads.step_frames(w, k), ptrs, stream=stream)
+        b.flush(stream=stream)
         host.copy_(ptrs, non_blocking=True)
         stream.synchronize()
         lat.append((time.perf_counter() - t) * 1e3)
 
-    # the same step with every stream tracked (temporal tracking, one frame
+    # the same steps with every stream tracked (temporal tracking, one frame
     # per stream per step: the component stage stays parallel)
     for i in range(n):
         b.set_tracking(i, True)
-    for k in range(2):
-        b.step(workloads.step_frames(w, k), ptrs, stream=stream)
+    run(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        b.step(workloads.step_frames(w, k), ptrs, stream=stream)
+    run(args.steps)
     torch.cuda.synchronize()
     track_sec = (time.perf_counter() - t0) / args.steps
     for i in range(n):
         b.set_tracking(i, False)
 
-    # kernel durations from their own dispatch events: the same kernels and
-    # grids, launched directly so that the events can be attached (the
-    # persistent kernel reports its whole launch under "classify")
-    persistent = tuning["mode"] in (fizi.BATCH_PERSISTENT, fizi.BATCH_PERSISTENT_GRAPH)
-    b.set_mode(fizi.BATCH_PERSISTENT if persistent else fizi.BATCH_DIRECT)
+    # kernel durations from their own dispatch events, in the launch form of
+    # the timed mode (the persistent kernel reports its whole launch under
+    # "classify")
+    form = TIMED_FORM[tuning["mode"]]
+    b.set_mode(form)
     b.stage_timing(True)
-    for k in range(args.steps):
-        b.step(workloads.step_frames(w, k), ptrs, stream=stream)
+    run(args.steps)
     torch.cuda.synchronize()
     st = b.stage_times()
     b.stage_timing(False)
@@ -123,13 +174,16 @@ def bench_batched(args, torch, fizi, workloads):
     stages_us = {k: round(v[0] * 1e3 / v[1], 2) for k, v in st.items() if v[1]}
     k_ms, k_n = st["classify"]
     k_avg = k_ms / 1e3 / max(1, k_n)
-    if persistent:
-        kernel, bpp = "k_step (fused gain, classify, morphology, components)", PATH_BYTES_PER_PX
+    if form == fizi.BATCH_PERSISTENT:
+        kernel, bpp, sym = "k_flow (fused gain, classify, morphology, components)", PATH_BYTES_PER_PX, None
     else:
-        kernel, bpp = f"k_classify<{tuning['cls_iters']}> (I_R1, I_R2, I_R3 per pixel)", CLASSIFY_BYTES_PER_PX
+        kernel = f"k_classify<{tuning['cls_iters']}> (I_R1, I_R2, I_R3 per pixel)"
+        bpp, sym = CLASSIFY_BYTES_PER_PX, f"_ZN4fizi12_GLOBAL__N_110k_classifyILi{tuning['cls_iters']}EEEvPNS_5TableE"
     achieved = bpp * px / k_avg / 1e9
     return dict(w=w, px=px, n=n, sec=sec, lat=lat, k_avg=k_avg, achieved=achieved, kernel=kernel, bpp=bpp,
-                tuning=tuning, stages_us=stages_us, track_sec=track_sec)
+                tuning=tuning, stages_us=stages_us, track_sec=track_sec, autotuned=autotuned,
+                timed_form=LAUNCH_NAMES[form], traffic=measured_traffic(sym) if sym else None,
+                code_hash=kernel_hash(sym) if sym else None)
 
 
 def bench_plain(args, torch, fizi, scene):
@@ -253,7 +307,9 @@ def bench_learn(args, torch, fizi, scene):
 def bench_soft(args, torch, scene):
     """Soft mask on the calibration workload (32 frames 1280x720): forward
     (3 B in, 4 B out per px), backward from dL/dm (3 + 4 B in), fused BCE
-    loss and gradient (3 + 1 B in)."""
+    loss and gradient (3 + 1 B in). Kernel times come from their own
+    dispatch events; `call_us` is the Python call as the autograd path makes
+    it (allocations and two launches included)."""
     from paper_1907_04393_amd import soft
     dev = torch.device("cuda:0")
     f, gt = scene.Scene(scene.calibration(), device=dev).hand_frames(0, 32, with_gt=True)
@@ -266,44 +322,126 @@ def bench_soft(args, torch, scene):
     torch.cuda.synchronize()
     reps = 20
     out = {"workload": "32 frames 1280x720 (29.5 Mpx), T = 0.5"}
-    for name, fn, bpp in (("forward", lambda: soft.soft_forward(f, prm, 0.5, out=m), 7),
-                          ("backward", lambda: soft.soft_backward(f, dm, prm, 0.5), 7),
-                          ("fused_bce", lambda: soft.soft_bce(f, gt, prm, 0.5), 4)):
+    for name, fn, bpp, stage in (("forward", lambda: soft.soft_forward(f, prm, 0.5, out=m), 7, "forward"),
+                                 ("backward", lambda: soft.soft_backward(f, dm, prm, 0.5), 7, "backward"),
+                                 ("fused_bce", lambda: soft.soft_bce(f, gt, prm, 0.5), 4, "backward")):
         fn()
         torch.cuda.synchronize()
+        soft.times()
+        soft.timing(True)
         t0 = time.perf_counter()
         for _ in range(reps):
             fn()
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / reps
-        out[name] = {"us": round(sec * 1e6, 1), "GBps": round(npx * bpp / sec / 1e9, 1),
-                     "frac": round(npx * bpp / sec / 1e9 / HBM_PEAK_GBS, 4)}
+        tm = soft.times()
+        soft.timing(False)
+        k_s = tm[stage][0] / 1e3 / max(1, tm[stage][1])
+        rec = {"kernel_us": round(k_s * 1e6, 2), "GBps": round(npx * bpp / k_s / 1e9, 1),
+               "frac": round(npx * bpp / k_s / 1e9 / HBM_PEAK_GBS, 4), "call_us": round(sec * 1e6, 1)}
+        if tm["final"][1]:
+            rec["final_reduce_us"] = round(tm["final"][0] * 1e3 / tm["final"][1], 2)
+        out[name] = rec
     return out
 
 
-def cpu_baseline(args, fizi, w):
-    """The oracle on a sample of the batched workload's frames (learning of
-    the sampled streams' models is set-up, not timed)."""
+def host_threads():
+    """Threads the CPU baseline may use: this process's CPU affinity, capped
+    by OMP_NUM_THREADS when that is set (the share of the host this job has)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, scene, w):
+    """The CPU oracle timed on this host beside the GPU: (1) on all host
+    threads, the batched workload (every stream, args.cpu_steps frame steps,
+    one stream per thread at a time); (2) one thread, the 320x240 workload in
+    full (30 learning + 100 hand frames); (3) one thread, the first
+    args.cpu_hd_frames hand frames of the 1920x1080 stream. Learning of the
+    batched streams' models is set-up, not timed."""
     from oracle import oracle
+    import concurrent.futures as cf
     import numpy as np
-    rng = np.random.default_rng(1)
-    n = len(w["specs"])
-    picks = rng.choice(n, size=args.cpu_streams, replace=False)
-    total_px, total_s, frames = 0, 0.0, 0
-    for i in picks:
-        sp, sc = w["specs"][i], w["scenes"][i]
+    nthr = host_threads()
+    specs, n = w["specs"], len(w["specs"])
+    frames = [f.cpu().numpy() for f in w["frames"]]
+
+    def learned(i):
+        sp = specs[i]
         m = oracle.Model(sp.width, sp.height)
-        m.learn(sc.bg_frames(0, 30).cpu().numpy())
-        hand = w["frames"][i].cpu().numpy()
-        for k in range(min(args.cpu_frames, hand.shape[0])):
-            t = time.perf_counter()
-            m.process(hand[k], frame_index=k)
-            total_s += time.perf_counter() - t
-            total_px += sp.width * sp.height
-            frames += 1
-    return {"value": round(total_px / total_s / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-            "sample": f"{frames} frames from {len(picks)} streams of the batched workload "
-                      f"({total_px / 1e6:.1f} Mpx), single thread, {total_s:.1f} s"}
+        m.learn(w["scenes"][i].bg_frames(0, 30).cpu().numpy())
+        return m
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(nthr) as pool:
+        models = list(pool.map(learned, range(n)))
+    log(f"cpu: {n} oracle models learned in {time.perf_counter() - t0:.1f} s on {nthr} threads")
+
+    def run(i):
+        for k in range(args.cpu_steps):
+            models[i].process(frames[i][k % w["pool"]], frame_index=k)
+
+    # largest streams first, so that the pool's tail is short
+    order = sorted(range(n), key=lambda i: -specs[i].width * specs[i].height)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(nthr) as pool:
+        list(pool.map(run, order))
+    all_s = time.perf_counter() - t0
+    all_px = args.cpu_steps * w["px_per_step"]
+    del models
+
+    # one thread: the 320x240 workload in full, learning included
+    sp0 = scene.small_plain()
+    sc0 = scene.Scene(sp0)
+    bg0, hand0 = sc0.bg_frames(0, sp0.n_bg).numpy(), sc0.hand_frames(0, sp0.n_hand).numpy()
+    t0 = time.perf_counter()
+    m0 = oracle.Model(sp0.width, sp0.height)
+    m0.learn(bg0)
+    for k in range(sp0.n_hand):
+        m0.process(hand0[k], frame_index=k)
+    small_s = time.perf_counter() - t0
+    small_px = sp0.width * sp0.height * (sp0.n_bg + sp0.n_hand)
+
+    # one thread: the 1920x1080 stream, first frames
+    sp1 = scene.hd_plain()
+    sc1 = scene.Scene(sp1, device="cuda:0")
+    m1 = oracle.Model(sp1.width, sp1.height)
+    m1.learn(sc1.bg_frames(0, sp1.n_bg).cpu().numpy())
+    hand1 = sc1.hand_frames(0, args.cpu_hd_frames).cpu().numpy()
+    t0 = time.perf_counter()
+    for k in range(hand1.shape[0]):
+        m1.process(hand1[k], frame_index=k)
+    hd_s = time.perf_counter() - t0
+    hd_px = sp1.width * sp1.height * hand1.shape[0]
+    return {"value": round(all_px / all_s / 1e6, 2), "unit": "Mpixel/s", "cores": nthr, "kind": "oracle",
+            "sample": f"batched workload: all {n} streams x {args.cpu_steps} frame steps "
+                      f"({all_px / 1e6:.0f} Mpx) on {nthr} host threads, one stream per thread at a time, "
+                      f"{all_s:.1f} s",
+            "cpu_model": cpu_model(),
+            "frames_per_s": round(n * args.cpu_steps / all_s, 2),
+            "single_thread": {
+                "320x240_full": {"frames": sp0.n_bg + sp0.n_hand, "seconds": round(small_s, 3),
+                                 "Mpixel_per_s": round(small_px / small_s / 1e6, 2),
+                                 "frames_per_s": round((sp0.n_bg + sp0.n_hand) / small_s, 1),
+                                 "note": "30 learning + 100 hand frames, learning included"},
+                "1920x1080": {"frames": int(hand1.shape[0]), "seconds": round(hd_s, 3),
+                              "Mpixel_per_s": round(hd_px / hd_s / 1e6, 2),
+                              "frames_per_s": round(hand1.shape[0] / hd_s, 2),
+                              "note": f"the first {hand1.shape[0]} of the stream's 2000 hand frames"}}}
 
 
 def main():
@@ -315,14 +453,14 @@ def main():
     ap.add_argument("--latency-steps", type=int, default=50)
     ap.add_argument("--plain-batch", type=int, default=256)
     ap.add_argument("--latency-frames", type=int, default=300)
-    ap.add_argument("--cpu-streams", type=int, default=4)
-    ap.add_argument("--cpu-frames", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=10, help="frame steps of the batched workload on the CPU")
+    ap.add_argument("--cpu-hd-frames", type=int, default=60, help="1920x1080 frames on one CPU thread")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time candidate launch shapes on the workload first and keep the fastest")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shape instead of the autotuner's pick")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a 1 GiB -> 1 GiB elementwise kernel 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -343,6 +481,8 @@ def main():
             torch.neg(a, out=c)
         torch.cuda.synchronize()
         del a, c
+    copy_gbs = copy_peak(torch)
+    log(f"device copy: {copy_gbs} GB/s")
     r = bench_batched(args, torch, fizi, workloads)
     mpxs = r["px"] / r["sec"] / 1e6
     fps = r["n"] / r["sec"]
@@ -361,7 +501,7 @@ def main():
         serving["budget_4GB_sessions_come_and_go"] = bench_serving(
             args, torch, workloads, budget=4e9, session_len=2.0, duration=min(6.0, args.serve_seconds))
         log("serving tight:", serving["budget_4GB_sessions_come_and_go"])
-    cpu = None if args.no_cpu else cpu_baseline(args, fizi, r["w"])
+    cpu = None if args.no_cpu else cpu_baseline(args, scene, r["w"])
     if cpu:
         log("cpu:", cpu)
     out = {
@@ -380,16 +520,20 @@ def main():
         "config": {"workload": "batched: 64 streams, resolutions drawn by seed from 640x480, 1280x720, "
                                "1920x1080, 3840x2160, RGB uint8, one frame per stream per step",
                    "px_per_step": r["px"], "streams": r["n"], "launch": LAUNCH_NAMES[r["tuning"]["mode"]],
-                   "tuning": r["tuning"]},
+                   "tuning": r["tuning"], "autotuned": r["autotuned"]},
         "frames_per_s": round(fps, 1),
         "latency_ms": {"p50": pct(r["lat"], 50), "p99": pct(r["lat"], 99),
-                       "mode": "one step of 64 frames submitted, pointers read back on the host"},
+                       "mode": "one step of 64 frames submitted and flushed, pointers read back on the host"},
         "path_roofline_frac": round(mpxs * 1e6 * PATH_BYTES_PER_PX / (HBM_PEAK_GBS * 1e9), 4),
+        "path_frac_of_copy": round(mpxs * 1e6 * PATH_BYTES_PER_PX / (copy_gbs * 1e9), 4),
         "roofline": {"bound": "hbm", "kernel": r["kernel"],
                      "achieved": round(r["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(r["achieved"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(r["kernel"]),
+                     "frac": round(r["achieved"] / HBM_PEAK_GBS, 4), "traffic": r["traffic"],
                      "avg_launch_us": round(r["k_avg"] * 1e6, 2),
-                     "bytes_per_launch": int(r["bpp"] * r["px"])},
+                     "bytes_per_px": r["bpp"], "bytes_per_launch": int(r["bpp"] * r["px"]),
+                     "timed_in": r["timed_form"], "code_hash": r["code_hash"],
+                     "measured_copy_GBps": copy_gbs,
+                     "frac_of_copy": round(r["achieved"] / copy_gbs, 4)},
         "stage_us": r["stages_us"],
         "tracking_ms_per_step": round(r["track_sec"] * 1e3, 4),
         "plain_single_stream": plain,

@@ -352,6 +352,16 @@ int fizi_batch_destroy(fizi_batch *b);
 int fizi_soft_forward(const uint8_t *d_frames, int64_t npx, const float params6[6], float T,
                       float *d_mask, void *stream);
 
+/* Measurement hook of the soft-mask calls (process-wide): with enable != 0
+ * each kernel launch records a HIP event pair from its own dispatch (at most
+ * 16384 per kernel between two reads); fizi_soft_times() waits for them,
+ * returns the summed milliseconds and launch counts per kernel, and clears
+ * them. Kernels: 0 the forward mask, 1 the per-block adjoint (or fused BCE)
+ * sums, 2 the final fixed-order reduction. */
+enum { FIZI_SOFT_STAGE_FORWARD = 0, FIZI_SOFT_STAGE_BACKWARD, FIZI_SOFT_STAGE_FINAL, FIZI_SOFT_NSTAGES };
+int fizi_soft_timing(int32_t enable);
+int fizi_soft_times(double *h_ms /* [FIZI_SOFT_NSTAGES] */, int64_t *h_launches /* [FIZI_SOFT_NSTAGES] */);
+
 /* Device workspace bytes the two calls below need (caller-owned). */
 size_t fizi_soft_workspace_bytes(int64_t npx);
 

@@ -12,6 +12,7 @@
 // step instead takes work items from an ordered queue (see TableHeader).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -138,6 +139,18 @@ struct StageEvents {
     hipEvent_t start = nullptr;
     hipEvent_t stop = nullptr;
 };
+
+// Launches go through hipExtLaunchKernelGGL so that, when the caller asks for
+// it, the start/stop events are taken from the kernel's own dispatch. `ev`
+// is evaluated more than once: pass a variable.
+#define FIZI_LAUNCH(kern, grid, block, lds, s, ev, ...)                                              \
+    do {                                                                                           \
+        if ((ev).start || (ev).stop)                                                               \
+            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, (ev).start, (ev).stop, 0, \
+                                  __VA_ARGS__);                                                    \
+        else                                                                                       \
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, __VA_ARGS__);                \
+    } while (0)
 
 // Kernel launchers (fizi_kernels.hip). Each returns the hipError_t of its launch.
 hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H, int rs,

@@ -1847,17 +1847,6 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n)
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Launches go through hipExtLaunchKernelGGL so that, when the caller asks for
-// it, the start/stop events are taken from the kernel's own dispatch.
-#define FIZI_LAUNCH(kern, grid, block, lds, s, ev, ...)                                              \
-    do {                                                                                           \
-        if ((ev).start || (ev).stop)                                                               \
-            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, (ev).start, (ev).stop, 0, \
-                                  __VA_ARGS__);                                                    \
-        else                                                                                       \
-            hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, __VA_ARGS__);                \
-    } while (0)
-
 hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H, int rs, hipStream_t s)
 {
     const int rows = (H + rs - 1) / rs;

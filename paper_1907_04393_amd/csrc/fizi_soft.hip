@@ -256,6 +256,17 @@ int soft_grid(long long npx)
     return (int)std::max<long long>(1, std::min<long long>(std::min(kSoftBlocksMax, n_cu * 8), groups));
 }
 
+// Measurement hook of the soft-mask calls: dispatch events of each kernel
+// (stages FIZI_SOFT_STAGE_*), like the contexts' stage clock.
+StageClock g_soft_clk;
+std::mutex g_soft_clk_mu;
+
+StageEvents soft_ev(int stage)
+{
+    std::lock_guard<std::mutex> lock(g_soft_clk_mu);
+    return g_soft_clk.next(stage);
+}
+
 int soft_backward(const uint8_t *frames, const float *dLdm, const uint8_t *gt, long long npx, const float p6[6],
                   float T, void *ws, size_t ws_bytes, double *out, int nout, void *stream)
 {
@@ -273,21 +284,24 @@ int soft_backward(const uint8_t *frames, const float *dLdm, const uint8_t *gt, l
     const int grid = soft_grid(npx);
     double *partial = static_cast<double *>(ws);
     const float inv_n = (float)(1.0 / (double)npx);
+    const StageEvents ev = soft_ev(FIZI_SOFT_STAGE_BACKWARD);
     if (gt) {
         if (reinterpret_cast<uintptr_t>(gt) % 4 == 0)
-            k_soft_bwd<true, true><<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, inv_n, partial);
+            FIZI_LAUNCH((k_soft_bwd<true, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, inv_n, partial);
         else
-            k_soft_bwd<true, false><<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, inv_n, partial);
+            FIZI_LAUNCH((k_soft_bwd<true, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, inv_n, partial);
     } else {
         if (reinterpret_cast<uintptr_t>(dLdm) % 16 == 0)
-            k_soft_bwd<false, true><<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, inv_n, partial);
+            FIZI_LAUNCH((k_soft_bwd<false, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, inv_n, partial);
         else
-            k_soft_bwd<false, false><<<grid, 256, 0, st>>>(frames, dLdm, gt, npx, s, inv_n, partial);
+            FIZI_LAUNCH((k_soft_bwd<false, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, inv_n,
+                        partial);
     }
     FIZI_HIP(hipGetLastError());
     // dL/dmu_b, dL/dmu_r, dL/ds_bb, dL/ds_br, dL/ds_rr, dL/dtheta, loss
     const SoftScale scale{{2.0, 2.0, 1.0, 2.0, 1.0, (double)s.inv_t, 1.0 / (double)npx, 0.0}};
-    k_soft_final<<<1, 256, 0, st>>>(partial, grid, scale, out, nout);
+    const StageEvents ev_final = soft_ev(FIZI_SOFT_STAGE_FINAL);
+    FIZI_LAUNCH(k_soft_final, 1, 256, 0, st, ev_final, partial, grid, scale, out, nout);
     FIZI_HIP(hipGetLastError());
     return FIZI_OK;
 }
@@ -350,8 +364,30 @@ int fizi_soft_forward(const uint8_t *d_frames, int64_t npx, const float params6[
     SoftParams s;
     FIZI_TRY(soft_params(params6, T, &s));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    k_soft_fwd<<<soft_grid(npx), 256, 0, st>>>(d_frames, npx, s, d_mask);
+    const StageEvents ev = soft_ev(FIZI_SOFT_STAGE_FORWARD);
+    FIZI_LAUNCH(k_soft_fwd, soft_grid(npx), 256, 0, st, ev, d_frames, npx, s, d_mask);
     FIZI_HIP(hipGetLastError());
+    return FIZI_OK;
+}
+
+int fizi_soft_timing(int32_t enable)
+{
+    std::lock_guard<std::mutex> lock(g_soft_clk_mu);
+    return g_soft_clk.enable(enable != 0);
+}
+
+int fizi_soft_times(double *h_ms, int64_t *h_launches)
+{
+    if (!h_ms || !h_launches)
+        return fail(FIZI_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(g_soft_clk_mu);
+    double ms[FIZI_NSTAGES];
+    int64_t n[FIZI_NSTAGES];
+    FIZI_TRY(g_soft_clk.read(ms, n));
+    for (int k = 0; k < FIZI_SOFT_NSTAGES; ++k) {
+        h_ms[k] = ms[k];
+        h_launches[k] = n[k];
+    }
     return FIZI_OK;
 }
 

@@ -145,6 +145,8 @@ def _extra_signatures(L):
         L.fizi_soft_bce.argtypes = [vp, vp, i64, P(ctypes.c_float), ctypes.c_float, vp,
                                     ctypes.c_size_t, vp, vp]
         L.fizi_soft_bce_static.argtypes = [vp, vp, i64, P(ctypes.c_float), ctypes.c_float, vp, vp]
+        L.fizi_soft_timing.argtypes = [i32]
+        L.fizi_soft_times.argtypes = [P(ctypes.c_double), P(ctypes.c_int64)]
 
 
 def check(rc):

@@ -98,6 +98,22 @@ class _SoftBCE(torch.autograd.Function):
                                                                        dtype=params.dtype), None
 
 
+STAGES = ("forward", "backward", "final")
+
+
+def timing(enable=True):
+    """Dispatch-event timing of the soft-mask kernels (process-wide)."""
+    fizi.check(fizi.lib().fizi_soft_timing(int(bool(enable))))
+
+
+def times() -> dict:
+    """{kernel: (summed ms, launches)} since the last read; waits for them."""
+    ms = (ctypes.c_double * 3)()
+    n = (ctypes.c_int64 * 3)()
+    fizi.check(fizi.lib().fizi_soft_times(ms, n))
+    return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+
 def soft_bce_static(frames, gt, params, T, out=None, stream=None):
     """The fused loss and gradient through the allocation-free entry point
     (its partial sums live in the library's static device array): returns

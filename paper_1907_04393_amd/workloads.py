@@ -12,8 +12,10 @@ import torch
 
 from . import fizi, scene
 
-# launch configuration of the multi-stream benchmark
-BATCH_MODE = fizi.BATCH_GRAPH
+# launch mode of the multi-stream benchmark before autotuning: steps
+# software-pipelined across frames (a step's outputs are complete after the
+# next step or a flush)
+BATCH_MODE = fizi.BATCH_PIPELINED
 
 
 def batched(n_streams=64, pool=4, n_bg=30, device="cuda", seed=2, log=None):

@@ -139,6 +139,7 @@ def test_batched_workload_full_size():
             ptrs = torch.empty((n, 56), dtype=torch.uint8, device=dev)
             fz = [torch.empty((sp.height, sp.width // 64), dtype=torch.int64, device=dev) for sp in w["specs"]]
             b.step(workloads.step_frames(w, k), ptrs, fizi=fz)
+            b.flush()
             torch.cuda.synchronize()
             outs.append((fizi.pointers_to_numpy(ptrs).copy(), [f.cpu().numpy() for f in fz]))
         res[mode] = outs
