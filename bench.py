@@ -54,7 +54,7 @@ TIMED_FORM = {0: 0, 1: 0, 2: 2, 3: 2, 4: 4, 5: 4}
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB -> 1 GiB
 # elementwise kernel gives), with the code hash of the kernel they were
 # taken on (the build writes lib/kernel_hashes.json)
-TRAFFIC = {"_ZN4fizi12_GLOBAL__N_110k_classifyILi4EEEvPNS_5TableE": ("6e994b625cb04815", 1714.1e6)}
+TRAFFIC = {"_ZN4fizi12_GLOBAL__N_110k_classifyILi8EEEvPNS_5TableE": ("74c2d01bd9939561", 1714.4e6)}
 
 
 def log(*a):
@@ -111,7 +111,10 @@ def bench_batched(args, torch, fizi, workloads):
 
     b.set_mode(workloads.BATCH_MODE)
     autotuned = None
-    if not args.no_autotune:
+    if args.shape:
+        c, r, g, m = (int(v) for v in args.shape.split(","))
+        b.set_tuning(cls_iters=c, morph_rows=r, grid_per_cu=g, mode=m)
+    elif not args.no_autotune:
         best, ms = b.autotune(workloads.step_frames(w, 0), ptrs, steps=10, stream=stream)
         autotuned = {"picked": best, "ms_per_step": round(ms, 4)}
         log(f"autotuned launch shape {best}: {ms:.3f} ms/step")
@@ -461,6 +464,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape instead of the autotuner's pick")
+    ap.add_argument("--shape", default="",
+                    help="fixed launch shape cls_iters,morph_rows,grid_per_cu,mode instead of the autotuner's "
+                         "pick (to profile one shape)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a 1 GiB -> 1 GiB elementwise kernel 3 times (reference for HBM counters)")
     args = ap.parse_args()
