@@ -106,6 +106,15 @@ typedef struct {
      * a hand reports no click and clears the count. 0..255, default 0
      * (0 and 1 report every frame's own click). No effect without tracking. */
     int32_t click_debounce;
+    /* Section 2, the Mouse module tracks the hand zone: with temporal
+     * tracking on and a hand in the previous frame, the hand is the
+     * component of area >= min_area nearest to the previous centroid pixel
+     * (the smallest squared distance from that pixel to one of its pixels,
+     * 0 for the component covering it) when that distance is at most
+     * track_radius pixels - ties to the larger area, then the smaller first
+     * raster index - else the largest component. 0 keeps only a component
+     * covering the previous centroid. 0..16384, default 64. */
+    int32_t track_radius;
 } fizi_params;
 
 /* One frame's pointer (56 bytes). When `present` is 0 every field except

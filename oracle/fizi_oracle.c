@@ -36,9 +36,13 @@
  *   R9  partial re-learning (Section 3.3) widens the model with running
  *       frames at the pixels their I_FIZI marks as background;
  *   R10 temporal tracking (Section 2, the Mouse module "tracks" the hand):
- *       when the previous frame had a hand, the component that covers its
- *       centroid pixel (floor of the coordinate sums over the area) keeps the
- *       hand if its area reaches min_area; otherwise R7 applies;
+ *       when the previous frame had a hand, with c its centroid pixel (floor
+ *       of the coordinate sums over the area), the hand is the component of
+ *       area >= min_area nearest to c - the smallest squared distance from c
+ *       to one of its pixels, 0 for the component that covers c - provided
+ *       that distance is at most track_radius pixels (ties: the larger area,
+ *       then the smallest first raster index); otherwise R7 applies. With
+ *       track_radius 0 only the component covering c keeps the hand;
  *   R12 adaptive thresholds (Section 3.2, "adaptive threshold or modify the
  *       dependent values consequently"): with brightness_mode 1 the pixels
  *       stay raw and the thresholds of I_R1 and I_R2 are brought to the
@@ -64,6 +68,9 @@ typedef struct {
     int32_t brightness_mode;      /* 0: correct the pixels, 1: scale the thresholds */
     int32_t click_debounce;       /* tracked streams: frames a click change needs
                                      (applied by the tracker of the Python oracle) */
+    int32_t track_radius;         /* tracked streams: farthest distance (pixels)
+                                     from the previous centroid pixel at which a
+                                     component still keeps the hand */
 } orc_params;
 
 typedef struct {
@@ -415,9 +422,11 @@ int orc_label(const uint8_t *m, int W, int H, int32_t *labels)
  * filled-box test. hand (nullable) receives the selected component. */
 /* The pointer of one I_FIZI mask. The hand zone is the component of largest
  * area (ties: smallest first raster index) - unless (track_x, track_y) is a
- * pixel (track_x >= 0) that lies in a component of area >= min_area: then
- * that component (reading R10, temporal tracking: the zone that covers the
- * previous frame's centroid keeps the hand). */
+ * point (track_x >= 0, the previous frame's centroid pixel) with a component
+ * of area >= min_area within track_radius of it: then the nearest such
+ * component, by the squared distance from the point to its nearest pixel
+ * (ties: larger area, then smaller first index) - reading R10, temporal
+ * tracking. The point may lie outside the image. */
 int orc_pointer_track(const uint8_t *fizi, int W, int H, const orc_params *p, uint32_t inv,
                       uint64_t frame_index, int32_t track_x, int32_t track_y, orc_pointer *out, uint8_t *hand);
 
@@ -453,10 +462,41 @@ int orc_pointer_track(const uint8_t *fizi, int W, int H, const orc_params *p, ui
         if (best == 0 || area[l] > area[best] || (area[l] == area[best] && first[l] < first[best]))
             best = l;
     }
-    if (track_x >= 0 && track_x < W && track_y >= 0 && track_y < H) {
-        int32_t l = labels[(size_t)track_y * W + track_x];
-        if (l && area[l] >= (uint64_t)(p->min_area > 0 ? p->min_area : 0))
-            best = l;
+    if (track_x >= 0 && K > 0) {
+        /* squared distance from the point to the nearest pixel of each
+         * component, by brute force over the pixels */
+        uint64_t *dmin = (uint64_t *)malloc(((size_t)K + 1) * sizeof(uint64_t));
+        if (!dmin) {
+            free(area);
+            free(first);
+            free(labels);
+            return -2;
+        }
+        for (int l = 0; l <= K; l++)
+            dmin[l] = UINT64_MAX;
+        for (size_t i = 0; i < npx; i++) {
+            int32_t l = labels[i];
+            if (!l)
+                continue;
+            int64_t dx = (int64_t)(i % W) - track_x, dy = (int64_t)(i / W) - track_y;
+            uint64_t d2 = (uint64_t)(dx * dx + dy * dy);
+            if (d2 < dmin[l])
+                dmin[l] = d2;
+        }
+        uint64_t amin = (uint64_t)(p->min_area > 0 ? p->min_area : 0);
+        uint64_t r2 = (uint64_t)p->track_radius * (uint64_t)p->track_radius;
+        int near = 0;
+        for (int l = 1; l <= K; l++) {
+            if (area[l] < amin || dmin[l] > r2)
+                continue;
+            if (near == 0 || dmin[l] < dmin[near] ||
+                (dmin[l] == dmin[near] && (area[l] > area[near] ||
+                                           (area[l] == area[near] && first[l] < first[near]))))
+                near = l;
+        }
+        if (near)
+            best = near;
+        free(dmin);
     }
     memset(out, 0, sizeof(*out));
     out->n_components = (uint32_t)K;

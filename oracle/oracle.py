@@ -26,7 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 DEFAULTS = dict(alpha1_cdeg=33000, alpha2_cdeg=7500, gray_S=20, bg_delta=10,
                 open_iters=1, close_iters=1, min_area=1, click_fill_permille=700,
                 gain_row_stride=8, gain_lo_q16=32768, gain_hi_q16=131072, brightness_mode=0,
-                click_debounce=0)
+                click_debounce=0, track_radius=64)
 
 
 class Params(ctypes.Structure):
@@ -315,8 +315,9 @@ class ClickDebounce:
 
 class Tracker:
     """Temporal tracking over a frame sequence (R10): each frame's hand is
-    the component that covers the previous frame's centroid pixel when it is
-    large enough, else the largest; its click is debounced (R13)."""
+    the component (of area >= min_area) nearest to the previous frame's
+    centroid pixel, within track_radius - the one covering it when there is
+    one - else the largest; its click is debounced (R13)."""
 
     def __init__(self, model):
         self.m = model

@@ -119,6 +119,7 @@ int fizi_default_params(fizi_params *out)
     out->gain_hi_q16 = 131072;
     out->brightness_mode = 0;
     out->click_debounce = 0;
+    out->track_radius = 64;
     return FIZI_OK;
 }
 

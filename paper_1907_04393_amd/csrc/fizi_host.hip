@@ -96,6 +96,8 @@ int validate(const fizi_geom *g, const fizi_params *p)
         return fail(FIZI_EINVAL, "brightness_mode must be 0 or 1");
     if (p->click_debounce < 0 || p->click_debounce > 255)
         return fail(FIZI_EINVAL, "click_debounce must be in 0..255");
+    if (p->track_radius < 0 || p->track_radius > 16384)
+        return fail(FIZI_EINVAL, "track_radius must be in 0..16384");
     return FIZI_OK;
 }
 
