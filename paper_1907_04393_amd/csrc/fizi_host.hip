@@ -200,6 +200,7 @@ void fill_job(const Model &m, int band, Job &J)
     J.scaled = m.p.brightness_mode;
     J.S_q16 = std::max((uint32_t)m.p.gray_S << 16, 1u);
     J.debounce = m.p.click_debounce;
+    J.track_r2 = (uint32_t)m.p.track_radius * (uint32_t)m.p.track_radius;
     J.hue = m.hue;
     J.track = m.tracking ? m.track : nullptr;
 }

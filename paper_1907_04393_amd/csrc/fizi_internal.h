@@ -81,6 +81,7 @@ struct Job {
     int32_t scaled;            // thresholds scaled by the gain instead of corrected pixels
     uint32_t S_q16;            // max(S * 2^16, 1): the gray tolerance against (max - min) * inv
     int32_t debounce;          // tracked streams: frames a change of the click needs
+    uint32_t track_r2;         // tracked streams: squared radius of the nearest-component pick
     HueTest hue;
     // accumulators (zero when the table is uploaded)
     // gain sums over usable sampled pixels, sampled row r adding to slot
@@ -89,7 +90,7 @@ struct Job {
     uint32_t nruns, flags, nlinks, nflag;
     uint32_t gain_done, morph_done;   // persistent step: finished gain tiles, morphology bands
     uint32_t ginv;                    // persistent step: 0x80000000 | inverse gain, once known
-    uint32_t pad2;
+    uint32_t pick;                    // deferred tracking: root of the largest component (or none)
 };
 
 // The persistent step's queue: segments of work items, in order

@@ -1455,28 +1455,61 @@ __device__ __forceinline__ void area_add(AreaTable &t, GLOBAL uint32_t *area, ui
     __hip_atomic_fetch_add(area + root, len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// One workgroup per frame: joins the band-local trees across band borders,
-// then finds roots, areas, the hand zone (largest area, ties to the smallest
-// first index), its sums and box, and writes the pointer.
-__device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool same_launch, AreaTable &tab)
+// Workgroup reductions (thread 0 and then every thread see the result).
+__device__ __forceinline__ uint32_t wg_min_u32(uint32_t v, uint32_t *s_tmp)
 {
-    __shared__ unsigned long long s_u64[2][kMaxWaves];
-    __shared__ uint32_t s_u32[5][kMaxWaves];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    Job *J = &T->jobs[j];
-    const int W = J->W, H = J->H, Wd = J->Wd;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1)
+        v = min(v, (uint32_t)__shfl_xor((int)v, o, kWave));
+    __syncthreads();
+    if (lane == 0)
+        s_tmp[wave] = v;
+    __syncthreads();
+    v = s_tmp[0];
+    for (int w = 1; w < nw; ++w)
+        v = min(v, s_tmp[w]);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wg_max_u64(unsigned long long v, unsigned long long *s_tmp)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const unsigned long long ov = __shfl_xor(v, o, kWave);
+        v = ov > v ? ov : v;
+    }
+    __syncthreads();
+    if (lane == 0)
+        s_tmp[wave] = v;
+    __syncthreads();
+    v = s_tmp[0];
+    for (int w = 1; w < nw; ++w)
+        v = s_tmp[w] > v ? s_tmp[w] : v;
+    return v;
+}
+
+constexpr uint32_t kNoRoot = 0xFFFFFFFFu;
+
+// Phases A-C of the component stage for one frame (one workgroup): the joins
+// across band and segment borders (and runs flagged when the pair list was
+// full, joined by reading I_FIZI), every run's root and each component's
+// area, and the largest component (ties to the smallest first index) as a
+// key area << 32 | ~root. Afterwards area[] holds every root's area and
+// each non-root run start's parent is one of its ancestors (see root_of).
+__device__ __forceinline__ void resolve_forest(Job *J, AreaTable &tab, uint32_t *ncomp_out,
+                                               unsigned long long *best_out)
+{
+    __shared__ unsigned long long s_u64[kMaxWaves];
+    __shared__ uint32_t s_u32[kMaxWaves];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int W = J->W, Wd = J->Wd;
     const uint32_t nr = min(ld_dev(&J->nruns), J->run_cap);
     const GLOBAL uint64_t *runs = G(reinterpret_cast<const uint64_t *>(J->runs));
     GLOBAL uint32_t *parent = G(J->parent);
     GLOBAL uint32_t *area = G(J->area);
     const GLOBAL uint64_t *fz = G(J->fizi);
-    GLOBAL uint64_t *hand = J->hand ? G(J->hand) : nullptr;
-    const uint32_t inv = job_gain(J, same_launch);
-    if (hand)
-        for (int i = threadIdx.x; i < H * Wd; i += blockDim.x)
-            hand[i] = 0ull;
-    // A: joins across band and segment borders (pairs of run starts), and
-    // runs flagged when the pair list was full, joined by reading I_FIZI
     if (threadIdx.x == 0)
         tab.overflow = 0;
     for (int i = threadIdx.x; i < kAreaSlots; i += blockDim.x) {
@@ -1515,14 +1548,14 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
         area_add(tab, area, root, rn.y);
     }
     __syncthreads();
-    // the table's areas go to the global array (the tracking test reads it)
+    // the table's areas go to the global array (tracking and the chain read it)
     for (int i = threadIdx.x; i < kAreaSlots; i += blockDim.x) {
         const uint32_t k = tab.key[i];
         if (k != kAreaEmpty)
             st_wg(area + k, tab.val[i]);
     }
-    // C: the largest component, ties to the smallest first index: from the
-    // table, or from every run when some root did not fit it
+    // C: the largest component: from the table, or from every run when some
+    // root did not fit it
     unsigned long long best = 0ull;
     if (!tab.overflow) {
         for (int i = threadIdx.x; i < kAreaSlots; i += blockDim.x) {
@@ -1542,164 +1575,378 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
             }
         }
     }
-    // one pass for both: per wave, then across the waves
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
         const unsigned long long ob = __shfl_xor(best, o, kWave);
         best = ob > best ? ob : best;
         ncomp += (uint32_t)__shfl_xor((int)ncomp, o, kWave);
     }
+    __syncthreads();
     if (lane == 0) {
-        s_u64[0][wave] = best;
-        s_u32[0][wave] = ncomp;
+        s_u64[wave] = best;
+        s_u32[wave] = ncomp;
     }
     __syncthreads();
-    best = s_u64[0][0];
-    ncomp = s_u32[0][0];
+    best = s_u64[0];
+    ncomp = s_u32[0];
     for (int w = 1; w < nw; ++w) {
-        best = s_u64[0][w] > best ? s_u64[0][w] : best;
-        ncomp += s_u32[0][w];
+        best = s_u64[w] > best ? s_u64[w] : best;
+        ncomp += s_u32[w];
     }
-    // temporal tracking: the component that covers the previous frame's
-    // centroid pixel keeps the hand when its area reaches min_area
+    *ncomp_out = ncomp;
+    *best_out = best;
+}
+
+// Root of the component of area >= amin covering pixel (tx, ty), or kNoRoot
+// (one thread; the forest is final).
+__device__ __forceinline__ uint32_t covering_root(const Job *J, int tx, int ty, uint32_t amin)
+{
+    if (tx < 0 || tx >= J->W || ty < 0 || ty >= J->H)
+        return kNoRoot;
+    const GLOBAL uint64_t *row = G(J->fizi) + (size_t)ty * J->Wd;
+    if (!((row[tx >> 6] >> (tx & 63)) & 1ull))
+        return kNoRoot;
+    const uint32_t start = (uint32_t)ty * (uint32_t)J->W + (uint32_t)(prev_zero(row, tx) + 1);
+    const uint32_t r = root_of(G(J->parent), start);
+    return ld_wg(G(J->area) + r) >= amin ? r : kNoRoot;
+}
+
+// The component of area >= amin nearest to (tx, ty) within sqrt(r2) pixels:
+// the smallest squared distance from the point to a pixel of it, ties to the
+// larger area, then the smaller first index; kNoRoot when none (whole
+// workgroup; the forest is final). A run's pixel nearest to the point is
+// its own clamp of tx, so two passes over the runs decide it: the least
+// distance, then the best key among the runs at that distance.
+__device__ __forceinline__ uint32_t nearest_root(const Job *J, int tx, int ty, uint32_t amin, uint32_t r2)
+{
+    __shared__ uint32_t s_min[kMaxWaves];
+    __shared__ unsigned long long s_key[kMaxWaves];
+    const int W = J->W;
+    const uint32_t nr = min(ld_dev(&J->nruns), J->run_cap);
+    const GLOBAL uint64_t *runs = G(reinterpret_cast<const uint64_t *>(J->runs));
+    GLOBAL uint32_t *parent = G(J->parent);
+    GLOBAL uint32_t *area = G(J->area);
+    auto dist2 = [&](uint2 rn) -> uint32_t {
+        const int y = (int)(rn.x / (uint32_t)W), xs = (int)(rn.x - (uint32_t)y * W), xe = xs + (int)rn.y - 1;
+        const int dx = tx < xs ? xs - tx : (tx > xe ? tx - xe : 0), dy = y - ty;
+        const unsigned long long d2 = (unsigned long long)((long long)dx * dx) + (unsigned long long)((long long)dy * dy);
+        return d2 > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)d2;
+    };
+    uint32_t dmin = 0xFFFFFFFFu;
+    for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+        const uint2 rn = unpack_run(runs[i]);
+        const uint32_t r = root_of(parent, rn.x);
+        if (ld_wg(area + r) >= amin)
+            dmin = min(dmin, dist2(rn));
+    }
+    dmin = wg_min_u32(dmin, s_min);
+    if (dmin > r2)
+        return kNoRoot;
+    unsigned long long key = 0ull;
+    for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+        const uint2 rn = unpack_run(runs[i]);
+        if (dist2(rn) != dmin)
+            continue;
+        const uint32_t r = root_of(parent, rn.x);
+        const uint32_t a = ld_wg(area + r);
+        if (a >= amin) {
+            const unsigned long long k = ((unsigned long long)a << 32) | (0xFFFFFFFFull - r);
+            key = k > key ? k : key;
+        }
+    }
+    key = wg_max_u64(key, s_key);
+    return key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : kNoRoot;
+}
+
+// The tracked pick given the previous frame's centroid pixel (valid: it had
+// a hand): the covering component, else the nearest within the radius;
+// kNoRoot for the largest (whole workgroup).
+__device__ __forceinline__ uint32_t tracked_pick(const Job *J, bool valid, int tx, int ty)
+{
     __shared__ uint32_t s_pick;
-    if (threadIdx.x == 0) {
-        uint32_t pick = 0xFFFFFFFFu;
-        const TrackState *ts = J->track;
-        if (ts && ts->valid) {
-            const int tx = ts->x, ty = ts->y;
-            if (tx >= 0 && tx < W && ty >= 0 && ty < H) {
-                const GLOBAL uint64_t *row = fz + (size_t)ty * Wd;
-                if ((row[tx >> 6] >> (tx & 63)) & 1ull) {
-                    const uint32_t start = (uint32_t)ty * (uint32_t)W + (uint32_t)(prev_zero(row, tx) + 1);
-                    const uint32_t r = find_root(parent, start);
-                    if ((long long)ld_wg(area + r) >= (long long)max(J->min_area, 0))
-                        pick = r;
-                }
+    const uint32_t amin = (uint32_t)max(J->min_area, 0);
+    if (threadIdx.x == 0)
+        s_pick = valid ? covering_root(J, tx, ty, amin) : kNoRoot;
+    __syncthreads();
+    uint32_t pick = s_pick;
+    __syncthreads();
+    if (valid && pick == kNoRoot && J->track_r2 > 0)
+        pick = nearest_root(J, tx, ty, amin, J->track_r2);
+    return pick;
+}
+
+struct ZoneStats {
+    unsigned long long sx, sy;
+    uint32_t x0, y0, x1, y1;
+};
+
+// Pass D: coordinate sums and box of component kstar, and its hand bits
+// (whole workgroup; thread 0 gets the totals). Membership walks each run to
+// its root without writing.
+__device__ __forceinline__ ZoneStats zone_stats(const Job *J, uint32_t kstar, GLOBAL uint64_t *hand)
+{
+    __shared__ unsigned long long s_u64[2][kMaxWaves];
+    __shared__ uint32_t s_u32[4][kMaxWaves];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int W = J->W, Wd = J->Wd;
+    const uint32_t nr = min(ld_dev(&J->nruns), J->run_cap);
+    const GLOBAL uint64_t *runs = G(reinterpret_cast<const uint64_t *>(J->runs));
+    GLOBAL uint32_t *parent = G(J->parent);
+    ZoneStats z{0, 0, 0xFFFFFFFFu, 0xFFFFFFFFu, 0, 0};
+    for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+        const uint2 rn = unpack_run(runs[i]);
+        if (root_of(parent, rn.x) != kstar)
+            continue;
+        const uint32_t y = rn.x / (uint32_t)W, xs = rn.x - y * (uint32_t)W;
+        const uint32_t xe = xs + rn.y - 1;
+        z.sx += (unsigned long long)rn.y * xs + (unsigned long long)rn.y * (rn.y - 1) / 2;
+        z.sy += (unsigned long long)rn.y * y;
+        z.x0 = min(z.x0, xs);
+        z.x1 = max(z.x1, xe);
+        z.y0 = min(z.y0, y);
+        z.y1 = max(z.y1, y);
+        if (hand) {
+            GLOBAL uint64_t *hr = hand + (size_t)y * Wd;
+            const int wa = (int)(xs >> 6), wb = (int)(xe >> 6);
+            for (int w = wa; w <= wb; ++w) {
+                const int lo = (w == wa) ? (int)(xs & 63) : 0;
+                const int hi = (w == wb) ? (int)(xe & 63) : 63;
+                const uint64_t m = (hi == 63 ? ~0ull : ((2ull << hi) - 1ull)) & (~0ull << lo);
+                __hip_atomic_fetch_or(hr + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
-        s_pick = pick;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        z.sx += __shfl_xor(z.sx, o, kWave);
+        z.sy += __shfl_xor(z.sy, o, kWave);
+        z.x0 = min(z.x0, (uint32_t)__shfl_xor((int)z.x0, o, kWave));
+        z.y0 = min(z.y0, (uint32_t)__shfl_xor((int)z.y0, o, kWave));
+        z.x1 = max(z.x1, (uint32_t)__shfl_xor((int)z.x1, o, kWave));
+        z.y1 = max(z.y1, (uint32_t)__shfl_xor((int)z.y1, o, kWave));
     }
     __syncthreads();
-    const uint32_t pick = s_pick;
-    const bool tracked = pick != 0xFFFFFFFFu;
+    if (lane == 0) {
+        s_u64[0][wave] = z.sx;
+        s_u64[1][wave] = z.sy;
+        s_u32[0][wave] = z.x0;
+        s_u32[1][wave] = z.y0;
+        s_u32[2][wave] = z.x1;
+        s_u32[3][wave] = z.y1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < nw; ++w) {
+            z.sx += s_u64[0][w];
+            z.sy += s_u64[1][w];
+            z.x0 = min(z.x0, s_u32[0][w]);
+            z.y0 = min(z.y0, s_u32[1][w]);
+            z.x1 = max(z.x1, s_u32[2][w]);
+            z.y1 = max(z.y1, s_u32[3][w]);
+        }
+    return z;
+}
+
+// The pointer of a frame's zone (thread 0): present when the frame has
+// components and the zone's area reaches min_area; the click is the
+// fill-ratio rule.
+__device__ __forceinline__ fizi_pointer make_pointer(const Job *J, bool present, uint32_t A, const ZoneStats &z,
+                                                     uint32_t ncomp, uint32_t inv)
+{
+    fizi_pointer o;
+    o.present = present ? 1 : 0;
+    o.click = 0;
+    o.reserved = 0;
+    o.area = 0;
+    o.sum_x = o.sum_y = 0;
+    o.x0 = o.y0 = o.x1 = o.y1 = 0;
+    if (present) {
+        o.area = A;
+        o.sum_x = z.sx;
+        o.sum_y = z.sy;
+        o.x0 = z.x0;
+        o.y0 = z.y0;
+        o.x1 = z.x1;
+        o.y1 = z.y1;
+        const unsigned long long box = (unsigned long long)(z.x1 - z.x0 + 1) * (z.y1 - z.y0 + 1);
+        o.click = (1000ull * A >= (unsigned long long)J->fill_pm * box) ? 1 : 0;
+    }
+    o.n_components = ncomp;
+    o.inv_gain_q16 = inv;
+    o.frame_index = J->frame_index;
+    return o;
+}
+
+// Click debouncing of a tracked stream (thread 0): a change is reported
+// once `debounce` consecutive frames show it; no hand clears the count.
+// Updates the stream's state and returns the reported click.
+__device__ __forceinline__ uint8_t debounce_click(uint32_t *state, bool present, uint8_t click, int debounce)
+{
+    uint32_t shown = *state & 1u, count = (*state >> 8) & 0xFFu;
+    if (!present) {
+        shown = 0;
+        count = 0;
+    } else if (click == shown) {
+        count = 0;
+    } else if (++count >= (uint32_t)debounce) {
+        shown = click;
+        count = 0;
+    }
+    *state = shown | (count << 8);
+    return (uint8_t)shown;
+}
+
+// One workgroup per frame: the forest, the hand zone, its sums and box, and
+// the pointer. A tracked frame picks its zone from the previous centroid
+// (tracked_pick) and debounces its click - unless `defer`: then the frame's
+// pointer is the largest component's, its root goes to J->pick, and the
+// tracking chain (k_track_chain) settles the tracked frames of the launch in
+// order afterwards.
+__device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool same_launch, AreaTable &tab,
+                                            bool defer = false)
+{
+    Job *J = &T->jobs[j];
+    const int H = J->H, Wd = J->Wd;
+    GLOBAL uint32_t *area = G(J->area);
+    GLOBAL uint64_t *hand = J->hand ? G(J->hand) : nullptr;
+    const uint32_t inv = job_gain(J, same_launch);
+    if (hand)
+        for (int i = threadIdx.x; i < H * Wd; i += blockDim.x)
+            hand[i] = 0ull;
+    uint32_t ncomp;
+    unsigned long long best;
+    resolve_forest(J, tab, &ncomp, &best);
+    TrackState *ts = J->track;
+    uint32_t pick = kNoRoot;
+    if (ts && !defer)
+        pick = tracked_pick(J, ts->valid != 0, ts->x, ts->y);
+    const bool tracked = pick != kNoRoot;
     const uint32_t A = tracked ? ld_wg(area + pick) : (uint32_t)(best >> 32);
     const uint32_t kstar = tracked ? pick : 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
     const bool present = ncomp > 0 && (long long)A >= (long long)J->min_area;
-    // D: sums and box of the selected component
-    unsigned long long sx = 0, sy = 0;
-    uint32_t x0 = 0xFFFFFFFFu, y0 = 0xFFFFFFFFu, x1 = 0, y1 = 0;
-    if (present) {
-        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) {
-            const uint2 rn = unpack_run(runs[i]);
-            if (root_of(parent, rn.x) != kstar)
-                continue;
-            const uint32_t y = rn.x / (uint32_t)W, xs = rn.x - y * (uint32_t)W;
-            const uint32_t xe = xs + rn.y - 1;
-            sx += (unsigned long long)rn.y * xs + (unsigned long long)rn.y * (rn.y - 1) / 2;
-            sy += (unsigned long long)rn.y * y;
-            x0 = min(x0, xs);
-            x1 = max(x1, xe);
-            y0 = min(y0, y);
-            y1 = max(y1, y);
-            if (hand) {
-                GLOBAL uint64_t *hr = hand + (size_t)y * Wd;
-                const int wa = (int)(xs >> 6), wb = (int)(xe >> 6);
-                for (int w = wa; w <= wb; ++w) {
-                    const int lo = (w == wa) ? (int)(xs & 63) : 0;
-                    const int hi = (w == wb) ? (int)(xe & 63) : 63;
-                    const uint64_t m = (hi == 63 ? ~0ull : ((2ull << hi) - 1ull)) & (~0ull << lo);
-                    __hip_atomic_fetch_or(hr + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            }
-        }
-    }
-    // sums and box in one pass: per wave, then thread 0 across the waves
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        sx += __shfl_xor(sx, o, kWave);
-        sy += __shfl_xor(sy, o, kWave);
-        x0 = min(x0, (uint32_t)__shfl_xor((int)x0, o, kWave));
-        y0 = min(y0, (uint32_t)__shfl_xor((int)y0, o, kWave));
-        x1 = max(x1, (uint32_t)__shfl_xor((int)x1, o, kWave));
-        y1 = max(y1, (uint32_t)__shfl_xor((int)y1, o, kWave));
-    }
-    if (lane == 0) {
-        s_u64[0][wave] = sx;
-        s_u64[1][wave] = sy;
-        s_u32[1][wave] = x0;
-        s_u32[2][wave] = y0;
-        s_u32[3][wave] = x1;
-        s_u32[4][wave] = y1;
-    }
-    __syncthreads();
+    ZoneStats z{0, 0, 0, 0, 0, 0};
+    if (present)
+        z = zone_stats(J, kstar, hand);
     if (threadIdx.x == 0) {
-        for (int w = 1; w < nw; ++w) {
-            sx += s_u64[0][w];
-            sy += s_u64[1][w];
-            x0 = min(x0, s_u32[1][w]);
-            y0 = min(y0, s_u32[2][w]);
-            x1 = max(x1, s_u32[3][w]);
-            y1 = max(y1, s_u32[4][w]);
-        }
-        fizi_pointer o;
-        o.present = present ? 1 : 0;
-        o.click = 0;
-        o.reserved = 0;
-        o.area = 0;
-        o.sum_x = o.sum_y = 0;
-        o.x0 = o.y0 = o.x1 = o.y1 = 0;
-        if (present) {
-            o.area = A;
-            o.sum_x = sx;
-            o.sum_y = sy;
-            o.x0 = x0;
-            o.y0 = y0;
-            o.x1 = x1;
-            o.y1 = y1;
-            const unsigned long long box = (unsigned long long)(x1 - x0 + 1) * (y1 - y0 + 1);
-            o.click = (1000ull * A >= (unsigned long long)J->fill_pm * box) ? 1 : 0;
-        }
-        o.n_components = ncomp;
-        o.inv_gain_q16 = inv;
-        o.frame_index = J->frame_index;
-        if (J->track) {
-            // click debouncing: a change is reported once `debounce`
-            // consecutive frames show it; no hand clears the count
-            TrackState *ts = J->track;
-            uint32_t shown = ts->click & 1u, count = (ts->click >> 8) & 0xFFu;
-            if (!present) {
-                shown = 0;
-                count = 0;
-            } else if (o.click == shown) {
-                count = 0;
-            } else if (++count >= (uint32_t)J->debounce) {
-                shown = o.click;
-                count = 0;
-            }
-            o.click = (uint8_t)shown;
-            ts->click = shown | (count << 8);
-        }
-        *J->out = o;
-        if (J->track) {
-            TrackState *ts = J->track;
+        fizi_pointer o = make_pointer(J, present, A, z, ncomp, inv);
+        if (defer) {
+            J->pick = ncomp > 0 ? kstar : kNoRoot;
+        } else if (ts) {
+            o.click = debounce_click(&ts->click, present, o.click, J->debounce);
             ts->valid = present ? 1 : 0;
             if (present) {
-                ts->x = (int32_t)(sx / A);
-                ts->y = (int32_t)(sy / A);
+                ts->x = (int32_t)(z.sx / A);
+                ts->y = (int32_t)(z.sy / A);
             }
         }
+        *J->out = o;
     }
     __syncthreads();
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_resolve(Table *__restrict__ T)
+__global__ __launch_bounds__(NT) void k_resolve(Table *__restrict__ T, int defer)
 {
     __shared__ AreaTable s_tab;
     const int nj = T->h.njobs;
     for (int j = blockIdx.x; j < nj; j += gridDim.x)
-        resolve_job(T, j, false, s_tab);
+        resolve_job(T, j, false, s_tab, defer != 0);
+}
+
+// Tracking of consecutive frames of one stream after a deferred component
+// stage (one workgroup; every job of the table belongs to the stream and
+// holds the largest component's pointer and root). Frame j's pick depends
+// on frame j - 1's centroid, so it is settled in order, but most of the work
+// is done first for all frames at once, on the guess that every earlier
+// frame kept its largest component: thread j tests whether that
+// component's centroid pixel lies in a component of frame j. In order, a
+// frame whose predecessor's actual centroid is the guessed one takes the
+// test's answer; otherwise thread 0 tests again; the nearest-component pass
+// runs (whole workgroup) only when no component covers the centroid, and a
+// frame whose pick is not its largest component gets its sums, box and hand
+// bits recomputed. Thread 0 then debounces the click and writes the pointer.
+constexpr int kChainMax = kMaxJobs;
+
+__global__ __launch_bounds__(kResolveThreads) void k_track_chain(Table *__restrict__ T)
+{
+    __shared__ uint32_t s_cover[kChainMax];
+    __shared__ int32_t s_gx[kChainMax], s_gy[kChainMax];   // guessed previous centroid, -1: no hand
+    __shared__ int32_t s_ax, s_ay;                        // actual previous centroid, -1: no hand
+    __shared__ uint32_t s_near;
+    const int nj = min(T->h.njobs, kChainMax);
+    if (nj == 0)
+        return;
+    TrackState *ts = T->jobs[0].track;
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) {
+        const Job *J = &T->jobs[j];
+        int gx = -1, gy = -1;
+        if (j == 0) {
+            if (ts->valid) {
+                gx = ts->x;
+                gy = ts->y;
+            }
+        } else {
+            const fizi_pointer *p = T->jobs[j - 1].out;
+            if (p->present) {
+                gx = (int32_t)(p->sum_x / p->area);
+                gy = (int32_t)(p->sum_y / p->area);
+            }
+        }
+        s_gx[j] = gx;
+        s_gy[j] = gy;
+        s_cover[j] = gx >= 0 ? covering_root(J, gx, gy, (uint32_t)max(J->min_area, 0)) : kNoRoot;
+    }
+    if (threadIdx.x == 0) {
+        s_ax = ts->valid ? ts->x : -1;
+        s_ay = ts->valid ? ts->y : -1;
+    }
+    __syncthreads();
+    for (int j = 0; j < nj; ++j) {
+        Job *J = &T->jobs[j];
+        const uint32_t amin = (uint32_t)max(J->min_area, 0);
+        const int ax = s_ax, ay = s_ay;
+        if (threadIdx.x == 0) {
+            uint32_t c = s_cover[j];
+            if (ax != s_gx[j] || ay != s_gy[j])
+                c = ax >= 0 ? covering_root(J, ax, ay, amin) : kNoRoot;
+            s_near = c;
+        }
+        __syncthreads();
+        uint32_t pick = s_near;
+        __syncthreads();
+        if (ax >= 0 && pick == kNoRoot && J->track_r2 > 0)
+            pick = nearest_root(J, ax, ay, amin, J->track_r2);
+        const uint32_t largest = J->pick;
+        GLOBAL uint64_t *hand = J->hand ? G(J->hand) : nullptr;
+        fizi_pointer o = *J->out;
+        if (pick != kNoRoot && pick != largest) {
+            // the tracked zone is not the largest: its own sums, box, hand bits
+            if (hand) {
+                for (int i = threadIdx.x; i < J->H * J->Wd; i += blockDim.x)
+                    hand[i] = 0ull;
+                __syncthreads();
+            }
+            const uint32_t A = ld_wg(G(J->area) + pick);
+            const ZoneStats z = zone_stats(J, pick, hand);
+            if (threadIdx.x == 0)
+                o = make_pointer(J, true, A, z, o.n_components, o.inv_gain_q16);
+        }
+        if (threadIdx.x == 0) {
+            const bool present = o.present != 0;
+            o.click = debounce_click(&ts->click, present, o.click, J->debounce);
+            *J->out = o;
+            s_ax = present ? (int32_t)(o.sum_x / o.area) : -1;
+            s_ay = present ? (int32_t)(o.sum_y / o.area) : -1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ts->valid = s_ax >= 0 ? 1 : 0;
+        if (s_ax >= 0) {
+            ts->x = s_ax;
+            ts->y = s_ay;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1920,12 +2167,20 @@ hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEve
 {
     if (njobs <= 0)
         return hipSuccess;
+    // consecutive tracked frames of one stream: every frame's forest and
+    // largest component at once, then the tracking chain in frame order
+    Table *tab = const_cast<Table *>(d_tab);
+    const int defer = serial ? 1 : 0;
     if (small)
-        FIZI_LAUNCH(k_resolve<kResolveThreadsSmall>, serial ? 1 : njobs, kResolveThreadsSmall, 0, s, ev,
-                    const_cast<Table *>(d_tab));
+        FIZI_LAUNCH(k_resolve<kResolveThreadsSmall>, njobs, kResolveThreadsSmall, 0, s, ev, tab, defer);
     else
-        FIZI_LAUNCH(k_resolve<kResolveThreads>, serial ? 1 : njobs, kResolveThreads, 0, s, ev,
-                    const_cast<Table *>(d_tab));
+        FIZI_LAUNCH(k_resolve<kResolveThreads>, njobs, kResolveThreads, 0, s, ev, tab, defer);
+    if (serial) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        k_track_chain<<<1, kResolveThreads, 0, s>>>(tab);
+    }
     return hipGetLastError();
 }
 

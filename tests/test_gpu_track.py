@@ -146,6 +146,94 @@ def test_batch_tracking_matches_oracle(mode):
     b.close()
 
 
+def _jump_sequence():
+    """A 10x10 square alone, then jumping 20 px right (its old centroid pixel
+    misses it) while a larger rectangle appears farther away, then growing
+    into a ring whose centroid is its hole, then gone, then back far away.
+    The oracle's picks are worked out in the tests below."""
+    masks = []
+    for k in range(7):
+        m = np.zeros((H, W), np.uint8)
+        if k >= 1:
+            _rect(m, 0, 40, 29, 59)                   # 30 x 20 = 600 px
+        if k == 0:
+            _rect(m, 40, 10, 49, 19)
+        elif k == 1:
+            _rect(m, 60, 10, 69, 19)
+        elif k in (2, 3):
+            _rect(m, 60, 10, 79, 29)
+            m[15:25, 65:75] = 0                       # ring, centroid (69, 19) in the hole
+        elif k == 5:
+            _rect(m, 100, 10, 109, 19)
+        masks.append(m)
+    masks = np.stack(masks)
+    bg = np.zeros((2, H, W, 3), np.uint8)
+    bg[...] = (40, 40, 90)
+    fr = np.repeat(bg[:1], len(masks), axis=0).copy()
+    fr[masks.astype(bool)] = (210, 140, 90)
+    return torch.from_numpy(bg), torch.from_numpy(fr)
+
+
+@pytest.mark.parametrize("radius", [64, 0])
+@pytest.mark.parametrize("chunk", [1, 3, 7])
+def test_plain_nearest_component_tracking(chunk, radius):
+    """Tracking with the nearest-component pick (default radius) and with
+    containment only (radius 0), in chunks of frames, against the oracle."""
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    params = dict(PARAMS, track_radius=radius)
+    bg, fr = _jump_sequence()
+    ref = _oracle_track(bg, fr, params)
+    areas = [r["pointer"]["area"] for r in ref]
+    # radius 64: the jumped square (100 px) and the ring (300 px) keep the
+    # hand over the larger rectangle; radius 0: the rectangle takes it
+    assert areas == ([100, 100, 300, 300, 600, 600, 600] if radius else [100, 600, 600, 600, 600, 600, 600])
+    ctx = fizi.Context(W, H, fizi.default_params(**params), chunk=chunk, device=dev)
+    ctx.learn_background(bg.to(dev))
+    ctx.set_tracking(True)
+    out = ctx.process_frames(fr.to(dev), want_fizi=True, want_hand=True)
+    torch.cuda.synchronize()
+    got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(out["pointers"])]
+    hand = fizi.unpack_bits(out["hand"], W)
+    for k in range(fr.shape[0]):
+        assert got[k] == ref[k]["pointer"], (chunk, radius, k, got[k], ref[k]["pointer"])
+        assert np.array_equal(hand[k], ref[k]["hand"]), (chunk, radius, k)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5])
+def test_batch_nearest_component_tracking(mode):
+    """The same sequence as one tracked stream of a batch (one frame per
+    step: the pick is made inside the component stage) beside an untracked
+    stream, in every launch mode."""
+    from oracle import oracle
+    from paper_1907_04393_amd import fizi
+    from test_gpu_plain import _blob_scene
+    dev = need_gpu()
+    bg, fr = _jump_sequence()
+    bgb, frb = _blob_scene(192, 70, 4, fr.shape[0], seed=29)
+    b = fizi.Batch([(W, H), (192, 70)], [fizi.default_params(**PARAMS), fizi.default_params()], device=dev)
+    b.set_mode(mode)
+    b.learn(0, bg.to(dev))
+    b.learn(1, bgb.to(dev))
+    b.set_tracking(0, True)
+    ref_a = _oracle_track(bg, fr, PARAMS)
+    mb = oracle.Model(192, 70)
+    mb.learn(bgb.numpy())
+    fa, fb = fr.to(dev), frb.to(dev)
+    bufs = []
+    for k in range(fr.shape[0]):
+        bufs.append(torch.empty((2, 56), dtype=torch.uint8, device=dev))
+        b.step([fa[k], fb[k]], bufs[-1])
+    b.flush()
+    torch.cuda.synchronize()
+    for k, ptrs in enumerate(bufs):
+        got = [fizi.pointer_dict(r) for r in fizi.pointers_to_numpy(ptrs)]
+        assert got[0] == ref_a[k]["pointer"], (mode, k, got[0], ref_a[k]["pointer"])
+        assert got[1] == mb.process(frb[k].numpy(), frame_index=k)["pointer"], (mode, k)
+    assert b.status() == 0
+    b.close()
+
+
 SHAPES = "FFHFFHHHFHHH"   # filled square (clicks) / hollow square (does not)
 
 
