@@ -115,6 +115,15 @@ typedef struct {
      * raster index - else the largest component. 0 keeps only a component
      * covering the previous centroid. 0..16384, default 64. */
     int32_t track_radius;
+    /* Section 3.2, over-exposure: an over-exposed hand looks white and the
+     * gray test removes it, so the Luminosity component is modified in the
+     * most obvious cases. With lum_hi in 128..254, a corrected pixel whose
+     * HSL lightness (max + min) / 2 exceeds lum_hi has it brought down to
+     * lum_hi with hue and HSL saturation kept before the gray test: its
+     * chroma becomes (max - min) (510 - 2 lum_hi) / (510 - max - min),
+     * compared exactly with S. The box and hue tests are unchanged. 0 (the
+     * default) turns it off; it needs brightness_mode 0. */
+    int32_t lum_hi;
 } fizi_params;
 
 /* One frame's pointer (56 bytes). When `present` is 0 every field except

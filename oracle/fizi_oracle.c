@@ -47,7 +47,14 @@
  *       dependent values consequently"): with brightness_mode 1 the pixels
  *       stay raw and the thresholds of I_R1 and I_R2 are brought to the
  *       frame's brightness instead (multiplied by the gain 2^16 / inv);
- *       the hue is the raw pixel's.
+ *       the hue is the raw pixel's;
+ *   R14 over-exposure filter (Section 3.2: an over-exposed hand looks white
+ *       and is removed as gray, so the Luminosity component is modified in
+ *       the most obvious cases): with lum_hi > 0, a corrected pixel whose HSL
+ *       lightness exceeds lum_hi / 255 has it lowered to lum_hi / 255, hue
+ *       and HSL saturation kept, before the gray test of I_R2; the box test
+ *       I_R1 and the hue test I_R3 see the corrected pixel (the hue does not
+ *       change with the lightness).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -71,6 +78,9 @@ typedef struct {
     int32_t track_radius;         /* tracked streams: farthest distance (pixels)
                                      from the previous centroid pixel at which a
                                      component still keeps the hand */
+    int32_t lum_hi;               /* over-exposure filter: 0 off, else the HSL
+                                     lightness (x 255) over-exposed pixels are
+                                     brought down to, 128..254 */
 } orc_params;
 
 typedef struct {
@@ -264,6 +274,31 @@ int orc_relearn(const uint8_t *frames, const uint8_t *fizi, int n, int W, int H,
     return 0;
 }
 
+/* ---- Section 3.2: the over-exposure filter on the Luminosity (reading R14) --
+ * HSL of an RGB pixel (channels over 255): lightness L = (max + min) / 2,
+ * chroma C = max - min, saturation s = C / (1 - |2L - 1|). Over-exposed means
+ * L > lum_hi / 255 (lum_hi >= 128, so L > 1/2 and 1 - |2L - 1| = 2 - 2L).
+ * Bringing L down to L' = lum_hi / 255 with the hue and s kept gives the
+ * chroma C' = s (2 - 2L'), all in units of 1/255:
+ *   C' = C (510 - 2 lum_hi) / (510 - (max + min)),
+ * and 0 for pure white (max + min = 510, C = 0). Returned as the exact
+ * fraction *num / *den (den > 0). */
+void orc_filtered_chroma(int r, int g, int b, int lum_hi, int64_t *num, int64_t *den)
+{
+    int mx = imax(r, imax(g, b)), mn = imin(r, imin(g, b));
+    int c = mx - mn, l2 = mx + mn;
+    if (lum_hi <= 0 || l2 <= 2 * lum_hi) {      /* not over-exposed: unchanged */
+        *num = c;
+        *den = 1;
+    } else if (l2 == 510) {                      /* white: no hue to keep */
+        *num = 0;
+        *den = 1;
+    } else {
+        *num = (int64_t)c * (510 - 2 * lum_hi);
+        *den = 510 - l2;
+    }
+}
+
 /* ---- Section 3.1: the three threshold images and their AND ---------------- */
 void orc_masks(const uint8_t *Fc, const uint8_t *bgmin, const uint8_t *bgmax, size_t npx,
                const orc_params *p, uint8_t *r1, uint8_t *r2, uint8_t *r3, uint8_t *raw)
@@ -277,9 +312,11 @@ void orc_masks(const uint8_t *Fc, const uint8_t *bgmin, const uint8_t *bgmax, si
             if ((int)v[c] < lo || (int)v[c] > hi)
                 out = 1;
         }
-        int mx = imax(v[0], imax(v[1], v[2]));
-        int mn = imin(v[0], imin(v[1], v[2]));
-        int notgray = (mx - mn) >= p->gray_S;
+        /* I_R2 on the pixel after the over-exposure filter (R14): its chroma
+         * C' = num / den against S */
+        int64_t num, den;
+        orc_filtered_chroma(v[0], v[1], v[2], p->lum_hi, &num, &den);
+        int notgray = num >= (int64_t)p->gray_S * den;
         int skin = orc_hue_in(v[0], v[1], v[2], p->alpha1_cdeg, p->alpha2_cdeg);
         if (r1) r1[i] = (uint8_t)out;
         if (r2) r2[i] = (uint8_t)notgray;

@@ -26,7 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 DEFAULTS = dict(alpha1_cdeg=33000, alpha2_cdeg=7500, gray_S=20, bg_delta=10,
                 open_iters=1, close_iters=1, min_area=1, click_fill_permille=700,
                 gain_row_stride=8, gain_lo_q16=32768, gain_hi_q16=131072, brightness_mode=0,
-                click_debounce=0, track_radius=64)
+                click_debounce=0, track_radius=64, lum_hi=0)
 
 
 class Params(ctypes.Structure):
@@ -79,6 +79,7 @@ def lib():
         L.orc_relearn.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(Params), u8p, u8p,
                                   P(ctypes.c_uint16), P(ctypes.c_uint32)]
         L.orc_masks.argtypes = [u8p, u8p, u8p, ctypes.c_size_t, P(Params), u8p, u8p, u8p, u8p]
+        L.orc_filtered_chroma.argtypes = [ctypes.c_int] * 4 + [P(ctypes.c_int64)] * 2
         L.orc_masks_scaled.argtypes = [u8p, u8p, u8p, ctypes.c_size_t, ctypes.c_uint32, P(Params),
                                        u8p, u8p, u8p, u8p]
         L.orc_erode.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int]
@@ -125,6 +126,14 @@ def hue_fraction(r, g, b):
     hn, hd = ctypes.c_int64(), ctypes.c_int64()
     ok = lib().orc_hue_fraction(int(r), int(g), int(b), ctypes.byref(hn), ctypes.byref(hd))
     return (hn.value, hd.value) if ok else None
+
+
+def filtered_chroma(r, g, b, lum_hi):
+    """Chroma (units of 1/255) of the pixel after the over-exposure filter
+    (R14), as an exact (numerator, denominator)."""
+    n, d = ctypes.c_int64(), ctypes.c_int64()
+    lib().orc_filtered_chroma(int(r), int(g), int(b), int(lum_hi), ctypes.byref(n), ctypes.byref(d))
+    return n.value, d.value
 
 
 def correct_value(v, inv) -> int:

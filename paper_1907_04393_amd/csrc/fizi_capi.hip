@@ -120,6 +120,7 @@ int fizi_default_params(fizi_params *out)
     out->brightness_mode = 0;
     out->click_debounce = 0;
     out->track_radius = 64;
+    out->lum_hi = 0;
     return FIZI_OK;
 }
 

@@ -98,6 +98,10 @@ int validate(const fizi_geom *g, const fizi_params *p)
         return fail(FIZI_EINVAL, "click_debounce must be in 0..255");
     if (p->track_radius < 0 || p->track_radius > 16384)
         return fail(FIZI_EINVAL, "track_radius must be in 0..16384");
+    if (p->lum_hi != 0 && (p->lum_hi < 128 || p->lum_hi > 254))
+        return fail(FIZI_EINVAL, "lum_hi must be 0 (off) or in 128..254");
+    if (p->lum_hi != 0 && p->brightness_mode != 0)
+        return fail(FIZI_EINVAL, "the over-exposure filter (lum_hi) works on corrected pixels: brightness_mode 0");
     return FIZI_OK;
 }
 

@@ -19,7 +19,7 @@ FIZI_OK, FIZI_EINVAL, FIZI_ESTATE, FIZI_ENOMEM, FIZI_EHIP, FIZI_ERANGE = 0, -1, 
 
 PARAM_FIELDS = ("alpha1_cdeg", "alpha2_cdeg", "gray_S", "bg_delta", "open_iters", "close_iters",
                 "min_area", "click_fill_permille", "gain_row_stride", "gain_lo_q16", "gain_hi_q16",
-                "brightness_mode", "click_debounce", "track_radius")
+                "brightness_mode", "click_debounce", "track_radius", "lum_hi")
 
 
 class Geom(ctypes.Structure):
