@@ -205,6 +205,8 @@ void fill_job(const Model &m, int band, Job &J)
     J.S_q16 = std::max((uint32_t)m.p.gray_S << 16, 1u);
     J.debounce = m.p.click_debounce;
     J.track_r2 = (uint32_t)m.p.track_radius * (uint32_t)m.p.track_radius;
+    J.S0 = m.p.gray_S;
+    J.lum2 = 2 * m.p.lum_hi;
     J.hue = m.hue;
     J.track = m.tracking ? m.track : nullptr;
 }

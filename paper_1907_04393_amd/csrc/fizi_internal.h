@@ -82,6 +82,8 @@ struct Job {
     uint32_t S_q16;            // max(S * 2^16, 1): the gray tolerance against (max - min) * inv
     int32_t debounce;          // tracked streams: frames a change of the click needs
     uint32_t track_r2;         // tracked streams: squared radius of the nearest-component pick
+    int32_t S0;                // gray tolerance S as given
+    int32_t lum2;              // over-exposure filter: 2 lum_hi, 0 when off
     HueTest hue;
     // accumulators (zero when the table is uploaded)
     // gain sums over usable sampled pixels, sampled row r adding to slot

@@ -446,8 +446,14 @@ struct ClsJob {
     int delta, S1;
     int scaled;
     uint32_t S_q16;
+    int S0, lum2;          // gray tolerance S; over-exposure filter: 2 lum_hi, 0 when off
     HueTest h;
 };
+
+// How a job's pixels are tested: corrected pixels, thresholds scaled to the
+// frame's brightness, or corrected pixels with the over-exposure filter
+// before the gray test.
+enum ClsKind { kCorrected = 0, kScaled = 1, kCorrectedLum = 2 };
 
 __device__ __forceinline__ ClsJob cls_job(const Job *J)
 {
@@ -460,8 +466,33 @@ __device__ __forceinline__ ClsJob cls_job(const Job *J)
     c.S1 = J->S1;
     c.scaled = J->scaled;
     c.S_q16 = J->S_q16;
+    c.S0 = J->S0;
+    c.lum2 = J->lum2;
     c.h = J->hue;
     return c;
+}
+
+__device__ __forceinline__ int cls_kind(const ClsJob &c)
+{
+    return c.scaled ? kScaled : (c.lum2 ? kCorrectedLum : kCorrected);
+}
+
+// I_R2 on a corrected pixel, with the over-exposure filter when LUM: a pixel
+// whose max + min exceeds 2 lum_hi has its HSL lightness brought down to
+// lum_hi (hue and saturation kept), which scales its chroma by
+// (510 - 2 lum_hi) / (510 - max - min); not gray when that chroma reaches S,
+// compared without division. Chroma > 0 is required in both cases (the hue
+// test needs it).
+template <bool LUM>
+__device__ __forceinline__ bool not_gray(const ClsJob &c, int mx, int mn)
+{
+    const int ch = mx - mn;
+    if (LUM) {
+        const int l2 = mx + mn;
+        if (l2 > c.lum2)
+            return ch >= 1 && ch * (510 - c.lum2) >= c.S0 * (510 - l2);
+    }
+    return ch >= c.S1;
 }
 
 // The inputs of one lane's 4 pixels: frame, background min and max (3 dwords
@@ -487,12 +518,13 @@ __device__ __forceinline__ void load_px4(const ClsJob &c, uint32_t p, uint32_t p
 // I_R1, I_R2 and I_R3 of one 1024-pixel unit of a frame (256 per wave, 4 per
 // lane) whose pixels from pend on are not classified; base is the wave's
 // first pixel (a multiple of 64), raw words at or past pend / 64 are not
-// written; x holds the lane's inputs (loaded by load_px4). SCALED: the
+// written; x holds the lane's inputs (loaded by load_px4). KIND: kScaled, the
 // thresholds follow the frame's brightness and the pixels stay raw.
-template <bool FLOW, bool SCALED>
+template <bool FLOW, int KIND>
 __device__ __forceinline__ void classify_px4(const ClsJob &c, uint32_t base, uint32_t pend, uint32_t inv,
                                              const Px4 &x)
 {
+    constexpr bool SCALED = KIND == kScaled;
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t p = base + 4u * lane;
     uint32_t bits = 0;
@@ -545,8 +577,8 @@ __device__ __forceinline__ void classify_px4(const ClsJob &c, uint32_t base, uin
             for (int k = 0; k < 4; ++k) {
                 if (out & (1u << k)) {
                     const int r = cv[3 * k], g = cv[3 * k + 1], b = cv[3 * k + 2];
-                    const int ch = max(max(r, g), b) - min(min(r, g), b);
-                    if (ch >= c.S1 && hue_in(r, g, b, c.h))
+                    if (not_gray<KIND == kCorrectedLum>(c, max(max(r, g), b), min(min(r, g), b)) &&
+                        hue_in(r, g, b, c.h))
                         bits |= 1u << k;
                 }
             }
@@ -566,7 +598,7 @@ __device__ __forceinline__ void classify_px4(const ClsJob &c, uint32_t base, uin
 // The wave's units of pixels [p0, p1) of a frame (p0 a multiple of 64):
 // 1024 pixels apart, each unit's inputs loaded one unit ahead into
 // alternating registers.
-template <bool FLOW, bool SCALED>
+template <bool FLOW, int KIND>
 __device__ __forceinline__ void classify_span_as(const ClsJob &c, uint32_t p0, uint32_t p1, uint32_t inv)
 {
     const uint32_t lanepx = 4u * (threadIdx.x & (kWave - 1));
@@ -575,12 +607,12 @@ __device__ __forceinline__ void classify_span_as(const ClsJob &c, uint32_t p0, u
     load_px4(c, base + lanepx, p1, a);
     while (base < p1) {
         load_px4(c, base + 1024u + lanepx, p1, b);
-        classify_px4<FLOW, SCALED>(c, base, p1, inv, a);
+        classify_px4<FLOW, KIND>(c, base, p1, inv, a);
         base += 1024u;
         if (base >= p1)
             break;
         load_px4(c, base + 1024u + lanepx, p1, a);
-        classify_px4<FLOW, SCALED>(c, base, p1, inv, b);
+        classify_px4<FLOW, KIND>(c, base, p1, inv, b);
         base += 1024u;
     }
 }
@@ -588,10 +620,11 @@ __device__ __forceinline__ void classify_span_as(const ClsJob &c, uint32_t p0, u
 template <bool FLOW>
 __device__ __forceinline__ void classify_span(const ClsJob &c, uint32_t p0, uint32_t p1, uint32_t inv)
 {
-    if (c.scaled)
-        classify_span_as<FLOW, true>(c, p0, p1, inv);
-    else
-        classify_span_as<FLOW, false>(c, p0, p1, inv);
+    switch (cls_kind(c)) {
+    case kScaled: classify_span_as<FLOW, kScaled>(c, p0, p1, inv); break;
+    case kCorrectedLum: classify_span_as<FLOW, kCorrectedLum>(c, p0, p1, inv); break;
+    default: classify_span_as<FLOW, kCorrected>(c, p0, p1, inv); break;
+    }
 }
 
 // Classify tile `tile` of frame j: ITERS consecutive 1024-pixel units.
@@ -610,10 +643,11 @@ __device__ __forceinline__ void classify_tile(Table *__restrict__ T, int j, int 
             break;
         Px4 x;
         load_px4(c, base + lanepx, npx, x);
-        if (c.scaled)
-            classify_px4<false, true>(c, base, npx, inv, x);
-        else
-            classify_px4<false, false>(c, base, npx, inv, x);
+        switch (cls_kind(c)) {
+        case kScaled: classify_px4<false, kScaled>(c, base, npx, inv, x); break;
+        case kCorrectedLum: classify_px4<false, kCorrectedLum>(c, base, npx, inv, x); break;
+        default: classify_px4<false, kCorrected>(c, base, npx, inv, x); break;
+        }
     }
 }
 
