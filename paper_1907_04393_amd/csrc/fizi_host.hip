@@ -111,14 +111,15 @@ Tuning tuning_for(int max_width, int max_ops)
 {
     (void)max_width;
     (void)max_ops;
-    // the autotuner's pick on the 64-stream 640x480..3840x2160 workload:
-    // short bands (more waves in the latency-bound morphology) and a grid of
-    // 32 blocks per CU for the streaming kernels (four rounds of resident
-    // blocks even out the tail)
+    // the autotuner's pick on the 64-stream 640x480..3840x2160 workload in
+    // the pipelined launch mode: 16-row bands and a grid of 64 blocks per CU
+    // for the streaming kernels (eight rounds of resident blocks even out the
+    // tail, and leave slots free often enough for the back half that runs
+    // beside them)
     Tuning t;
     t.cls_iters = 4;
-    t.grid_per_cu = 32;
-    t.morph_rows = 8;
+    t.grid_per_cu = 64;
+    t.morph_rows = 16;
     return t;
 }
 

@@ -15,6 +15,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSoftBlocksMax = 2048;
 constexpr int kSoftOut = 8;        // 6 gradients, loss, unused
+constexpr int kSoftU = 4;          // pixel groups per thread and iteration of the adjoint
 
 struct SoftParams {
     float mu_b, mu_r;
@@ -26,9 +27,10 @@ struct SoftPx {
     float m, z, d, h, e, ub, ur;   // h = 1 / (2 d) (0 at d = 0), e = exp(-|z|)
 };
 
-// Three transcendentals per pixel: one reciprocal square root gives d and
-// 1 / (2 d), one exponential gives the sigmoid (and the BCE's softplus), one
-// reciprocal.
+// Three transcendentals per pixel, each one hardware instruction (about one
+// ulp, far inside the relative 1e-4 the calibration form needs): one
+// reciprocal square root gives d and 1 / (2 d), one exponential gives the
+// sigmoid (and the BCE's softplus), one reciprocal.
 __device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftParams &s)
 {
     const float cb = fmaf(0.5f, b, fmaf(-0.331264f, g, fmaf(-0.168736f, r, 128.0f)));
@@ -38,12 +40,12 @@ __device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftP
     o.ub = fmaf(s.p_bb, db, s.p_br * dr);
     o.ur = fmaf(s.p_br, db, s.p_rr * dr);
     const float q = fmaxf(fmaf(db, o.ub, dr * o.ur), 0.0f);
-    const float rs = q > 0.0f ? __frsqrt_rn(q) : 0.0f;
+    const float rs = q > 0.0f ? __builtin_amdgcn_rsqf(q) : 0.0f;
     o.d = q * rs;
     o.h = 0.5f * rs;
     o.z = (s.theta - o.d) * s.inv_t;
     o.e = __expf(-fabsf(o.z));
-    const float rc = __frcp_rn(1.0f + o.e);
+    const float rc = __builtin_amdgcn_rcpf(1.0f + o.e);
     o.m = o.z >= 0.0f ? rc : o.e * rc;
     return o;
 }
@@ -129,15 +131,16 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ fr
     const long long groups = npx / 4;
     const uint32_t *f = reinterpret_cast<const uint32_t *>(frames);
     const long long stride = (long long)gridDim.x * blockDim.x;
-    // groups gi and gi + stride together: their loads in flight at once, their
-    // 8 pixels summed in FP32 before the FP64 accumulators
-    for (long long g0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; g0 < groups; g0 += 2 * stride) {
-        uint32_t w[2][3];
-        float dm[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-        uint32_t y4[2] = {0, 0};
-        bool have[2];
+    // groups gi, gi + stride, ... (kSoftU of them) together: their loads in
+    // flight at once, their pixels summed in FP32 before the FP64
+    // accumulators
+    for (long long g0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; g0 < groups; g0 += kSoftU * stride) {
+        uint32_t w[kSoftU][3];
+        float dm[kSoftU][4] = {};
+        uint32_t y4[kSoftU] = {};
+        bool have[kSoftU];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < kSoftU; ++u) {
             const long long gi = g0 + u * stride;
             have[u] = gi < groups;
             if (!have[u])
@@ -165,9 +168,9 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ fr
                     dm[u][k] = dLdm[4 * gi + k];
             }
         }
-        float a8[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};   // up to 8 pixels in FP32
+        float a8[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};   // up to 4 kSoftU pixels in FP32
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < kSoftU; ++u)
             if (have[u])
                 soft_group<BCE>(w[u][0], w[u][1], w[u][2], dm[u], y4[u], s, inv_n, a8);
 #pragma unroll
@@ -205,26 +208,26 @@ struct SoftScale {
     double k[kSoftOut];
 };
 
-// Fixed-order sum of the block partials: out[k] = sum_b partial[b][k] * scale[k].
+// Fixed-order sum of the block partials: out[k] = sum_b partial[b][k] *
+// scale[k], one workgroup per output k (each a fixed tree, so the result
+// does not depend on timing).
 __global__ __launch_bounds__(256) void k_soft_final(const double *__restrict__ partial, int nblocks, SoftScale scale,
-                                                    double *__restrict__ out, int nout)
+                                                    double *__restrict__ out)
 {
     __shared__ double s[256];
-    for (int k = 0; k < nout; ++k) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-            v += partial[b * kSoftOut + k];
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h)
-                s[threadIdx.x] += s[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0)
-            out[k] = s[0] * scale.k[k];
+    const int k = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        v += partial[b * kSoftOut + k];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            s[threadIdx.x] += s[threadIdx.x + h];
         __syncthreads();
     }
+    if (threadIdx.x == 0)
+        out[k] = s[0] * scale.k[k];
 }
 
 int soft_params(const float p6[6], float T, SoftParams *s)
@@ -301,7 +304,7 @@ int soft_backward(const uint8_t *frames, const float *dLdm, const uint8_t *gt, l
     // dL/dmu_b, dL/dmu_r, dL/ds_bb, dL/ds_br, dL/ds_rr, dL/dtheta, loss
     const SoftScale scale{{2.0, 2.0, 1.0, 2.0, 1.0, (double)s.inv_t, 1.0 / (double)npx, 0.0}};
     const StageEvents ev_final = soft_ev(FIZI_SOFT_STAGE_FINAL);
-    FIZI_LAUNCH(k_soft_final, 1, 256, 0, st, ev_final, partial, grid, scale, out, nout);
+    FIZI_LAUNCH(k_soft_final, nout, 256, 0, st, ev_final, partial, grid, scale, out);
     FIZI_HIP(hipGetLastError());
     return FIZI_OK;
 }
