@@ -13,9 +13,12 @@ namespace {
 constexpr int kRing = 65536;   // pointers kept for get_pointer
 constexpr int kRecs = 64;
 
-// State block: model | job tables | chunk pointers | chunk scratch slots.
+// State block: model | job tables | chunk pointers | chunk scratch slots |
+// a second raw-mask buffer per slot (consecutive chunks of a call alternate
+// between the two, so that a chunk's classify never writes the bits the
+// previous chunk's morphology is reading).
 struct CtxLayout {
-    size_t model, tables, ptrs, slots, slot_stride, total;
+    size_t model, tables, ptrs, slots, slot_stride, raw2, raw2_stride, total;
 };
 
 CtxLayout ctx_layout(const fizi_geom &g, const fizi_params &p, int chunk)
@@ -31,6 +34,9 @@ CtxLayout ctx_layout(const fizi_geom &g, const fizi_params &p, int chunk)
     L.slot_stride = align256(slot_bytes(g));
     L.slots = off;
     off += (size_t)chunk * L.slot_stride;
+    L.raw2_stride = align256((size_t)g.height * (g.width / 64) * 8);
+    L.raw2 = off;
+    off += (size_t)chunk * L.raw2_stride;
     L.total = align256(off);
     return L;
 }
@@ -58,6 +64,11 @@ struct fizi_ctx {
     hipStream_t last_stream = nullptr;
     bool have_last = false;
     uint64_t next_frame = 0;
+    // calls of several chunks: the back half of a chunk (morphology,
+    // components, pointer copies) on a side stream beside the next chunk's
+    // front, the job tables going up on their own stream
+    hipStream_t side = nullptr, up = nullptr;
+    hipEvent_t up_ev[2] = {}, cls_ev[2] = {}, join_ev[2] = {};
 };
 
 namespace {
@@ -180,6 +191,17 @@ int fizi_create(const fizi_geom *geom, const fizi_params *params, int32_t chunk_
                                      hipHostMallocDefault);
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            e = hipEventCreateWithFlags(&c->up_ev[k], hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&c->cls_ev[k], hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming);
+        }
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&c->up, hipStreamNonBlocking);
         if (e != hipSuccess)
             rc = fail(FIZI_EHIP, std::string("fizi_create: ") + hipGetErrorString(e));
     }
@@ -240,6 +262,10 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
     FIZI_TRY(order_after_previous(c, s));
     const size_t W = c->m.g.width, H = c->m.g.height, px = W * H, words = H * (W / 64);
     fizi_pointer *internal = reinterpret_cast<fizi_pointer *>(c->d + c->L.ptrs);
+    // several chunks: each chunk's back half runs beside the next chunk's
+    // front (on the side stream; s joins it before the call ends)
+    const bool pipelined = n_frames > c->chunk;
+    int par = 0, prev_join = -1, last_slot = -1;
     for (int f0 = 0; f0 < n_frames; f0 += c->chunk) {
         const int k = std::min(c->chunk, n_frames - f0);
         int slot;
@@ -250,6 +276,8 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
             Job &J = T.jobs[i];
             fill_job(c->m, c->tune.morph_rows, J);
             set_scratch(J, slot_at(c->m.g, c->d + c->L.slots + (size_t)i * c->L.slot_stride));
+            if (pipelined && par)
+                J.raw = reinterpret_cast<uint64_t *>(c->d + c->L.raw2 + (size_t)i * c->L.raw2_stride);
             const size_t f = (size_t)(f0 + i);
             J.frame = d_frames + f * px * 3;
             if (d_fizi_bits)
@@ -259,25 +287,60 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
             J.frame_index = fbase + (uint64_t)i;
         }
         set_prefixes(T, k, c->tune);
-        FIZI_HIP(hipMemcpyAsync(c->ring.d[slot], &T, table_bytes(k), hipMemcpyHostToDevice, s));
-        FIZI_TRY(run_pipeline(c->ring.d[slot], T, k, k, (int)(W / 64), morph_ops(c->m.p), c->tune, c->n_cu,
-                              false, s, &c->clk));
         const bool last = f0 + k == n_frames;
+        // the stream the chunk's back half and pointer copies go to
+        hipStream_t bs = s;
+        if (pipelined) {
+            FIZI_HIP(hipMemcpyAsync(c->ring.d[slot], &T, table_bytes(k), hipMemcpyHostToDevice, c->up));
+            FIZI_HIP(hipEventRecord(c->up_ev[par], c->up));
+            FIZI_HIP(hipStreamWaitEvent(s, c->up_ev[par], 0));
+            FIZI_TRY(run_front(c->ring.d[slot], T, k, c->tune, c->n_cu, false, s, &c->clk));
+            FIZI_HIP(hipEventRecord(c->cls_ev[par], s));
+            FIZI_HIP(hipStreamWaitEvent(c->side, c->cls_ev[par], 0));
+            bs = c->side;
+            FIZI_TRY(run_back(c->ring.d[slot], T, k, k, (int)(W / 64), morph_ops(c->m.p), c->tune, c->n_cu,
+                              false, bs, &c->clk, true));
+        } else {
+            FIZI_HIP(hipMemcpyAsync(c->ring.d[slot], &T, table_bytes(k), hipMemcpyHostToDevice, s));
+            FIZI_TRY(run_pipeline(c->ring.d[slot], T, k, k, (int)(W / 64), morph_ops(c->m.p), c->tune, c->n_cu,
+                                  false, s, &c->clk));
+        }
         if (!d_pointers)
-            FIZI_TRY(copy_to_ring(c, internal, fbase, k, s));
-        else if (last)
-            FIZI_TRY(copy_to_ring(c, d_pointers, c->next_frame, n_frames, s));
-        FIZI_TRY(c->ring.finish(slot, s));
+            FIZI_TRY(copy_to_ring(c, internal, fbase, k, bs));
+        FIZI_TRY(c->ring.finish(slot, bs));
+        if (pipelined) {
+            FIZI_HIP(hipEventRecord(c->join_ev[par], c->side));
+            // the chunk before this one is joined after this classify: the
+            // next classify reuses its raw buffers
+            if (prev_join >= 0)
+                FIZI_HIP(hipStreamWaitEvent(s, c->join_ev[prev_join], 0));
+            prev_join = par;
+            par ^= 1;
+        }
+        last_slot = slot;
         // the ring holds a chunk's pointers once its own copy is done
         // (internal pointers) or once the call's single copy is done
-        if (!d_pointers || last) {
+        if (!d_pointers) {
             fizi_ctx::Rec &r = c->recs[c->next_rec];
             c->next_rec = (c->next_rec + 1) % kRecs;
-            r.f0 = d_pointers ? c->next_frame : fbase;
+            r.f0 = fbase;
             r.f1 = fbase + k;
             r.slot = slot;
             r.valid = true;
         }
+        (void)last;
+    }
+    if (pipelined)
+        FIZI_HIP(hipStreamWaitEvent(s, c->join_ev[prev_join], 0));
+    if (d_pointers) {
+        FIZI_TRY(copy_to_ring(c, d_pointers, c->next_frame, n_frames, s));
+        FIZI_TRY(c->ring.finish(last_slot, s));
+        fizi_ctx::Rec &r = c->recs[c->next_rec];
+        c->next_rec = (c->next_rec + 1) % kRecs;
+        r.f0 = c->next_frame;
+        r.f1 = c->next_frame + (uint64_t)n_frames;
+        r.slot = last_slot;
+        r.valid = true;
     }
     c->next_frame += (uint64_t)n_frames;
     return mark_last(c, s);
@@ -342,8 +405,13 @@ int fizi_destroy(fizi_ctx *c)
     c->clk.destroy();
     if (c->h_ring)
         (void)hipHostFree(c->h_ring);
-    if (c->order_ev)
-        (void)hipEventDestroy(c->order_ev);
+    for (hipEvent_t e : {c->order_ev, c->up_ev[0], c->up_ev[1], c->cls_ev[0], c->cls_ev[1], c->join_ev[0],
+                         c->join_ev[1]})
+        if (e)
+            (void)hipEventDestroy(e);
+    for (hipStream_t st : {c->side, c->up})
+        if (st)
+            (void)hipStreamDestroy(st);
     delete c;
     return FIZI_OK;
 }
