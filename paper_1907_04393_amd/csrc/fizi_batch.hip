@@ -322,7 +322,7 @@ int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_para
         b->max_ops = std::max(b->max_ops, morph_ops(params[i]));
     }
     b->max_wd = max_w / 64;
-    b->tune = tuning_for(max_w, b->max_ops);
+    b->tune = tuning_for(max_w, b->max_ops, true);
     b->persist = b->d + L.persist;
     int rc = device_cu_count(&b->device, &b->n_cu);
     if (rc == FIZI_OK)

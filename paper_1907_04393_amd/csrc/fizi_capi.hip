@@ -182,7 +182,7 @@ int fizi_create(const fizi_geom *geom, const fizi_params *params, int32_t chunk_
     c->d = static_cast<uint8_t *>(d_state);
     c->L = L;
     model_at(c->m, *geom, *params, c->d + L.model);
-    c->tune = tuning_for(geom->width, morph_ops(*params));
+    c->tune = tuning_for(geom->width, morph_ops(*params), false);
     int rc = device_cu_count(&c->device, &c->n_cu);
     if (rc == FIZI_OK)
         rc = c->ring.init(c->d + L.tables);

@@ -36,8 +36,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int validate(const fizi_geom *g, const fizi_params *p);
 HueTest make_hue(int a1, int a2);
-// Launch shapes for frames up to max_width wide and max_ops morphology steps.
-Tuning tuning_for(int max_width, int max_ops);
+// Launch shapes for frames up to max_width wide and max_ops morphology steps,
+// for a multi-stream batch or a single-stream context.
+Tuning tuning_for(int max_width, int max_ops, bool batch);
 int morph_ops(const fizi_params &p);
 
 // Background model of one stream (Section 3.1 (i)) and its reference

@@ -325,3 +325,54 @@ def test_default_cuda_device_accepts_indexed_frames():
     torch.cuda.synchronize()
     assert fizi.pointer_dict(fizi.pointers_to_numpy(ptrs)[0])["present"] == 0
     b.close()
+
+
+@pytest.mark.parametrize("mode", (4, 5))
+def test_pipelined_outputs_at_every_completion_point(mode):
+    """In the pipelined modes a step's outputs are complete once the next
+    step has completed, and after every call that flushes or drains: an
+    empty step leaves the pending one pending (flush completes it), learning
+    flushes, status() and set_mode() drain."""
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    specs, params, data = _streams()
+    n = len(specs)
+    b = fizi.Batch([(sp.width, sp.height) for sp in specs],
+                   [fizi.default_params(**p) for p in params], device=dev)
+    b.set_mode(mode)
+    for i, (bg, _) in enumerate(data):
+        b.learn(i, bg.to(dev))
+    hands = [h.to(dev) for _, h in data]
+    orc = _oracle(specs, params, data)
+    refs = [[m.process(hand[k].numpy(), frame_index=k)["pointer"] for k in range(5)] for m, hand in orc]
+
+    def check(ptrs, k):
+        got = fizi.pointers_to_numpy(ptrs)
+        for i in range(n):
+            assert fizi.pointer_dict(got[i]) == refs[i][k], (mode, k, i)
+
+    def new():
+        return torch.full((n, 56), 0xAB, dtype=torch.uint8, device=dev)
+
+    p = [new() for _ in range(5)]
+    b.step([h[0] for h in hands], p[0])
+    b.step([h[1] for h in hands], p[1])
+    torch.cuda.synchronize()
+    check(p[0], 0)                              # completed by the next step
+    idle = new()
+    b.step([None] * n, idle)                    # nothing to do: step 1 stays pending
+    b.flush()
+    torch.cuda.synchronize()
+    check(p[1], 1)
+    assert (idle.cpu().numpy() == 0xAB).all()
+    b.step([h[2] for h in hands], p[2])
+    b.learn(0, data[0][0].to(dev))              # the same frames again: the model does not change
+    torch.cuda.synchronize()
+    check(p[2], 2)
+    b.step([h[3] for h in hands], p[3])
+    assert b.status() == 0                      # drains
+    check(p[3], 3)
+    b.step([h[4] for h in hands], p[4])
+    b.set_mode(fizi.BATCH_GRAPH)                # drains
+    check(p[4], 4)
+    b.close()
