@@ -1889,28 +1889,42 @@ __global__ __launch_bounds__(NT) void k_resolve(Table *__restrict__ T, int defer
 
 // Tracking of consecutive frames of one stream after a deferred component
 // stage (one workgroup; every job of the table belongs to the stream and
-// holds the largest component's pointer and root). Frame j's pick depends
-// on frame j - 1's centroid, so it is settled in order, but most of the work
-// is done first for all frames at once, on the guess that every earlier
-// frame kept its largest component: thread j tests whether that
-// component's centroid pixel lies in a component of frame j. In order, a
-// frame whose predecessor's actual centroid is the guessed one takes the
-// test's answer; otherwise thread 0 tests again; the nearest-component pass
-// runs (whole workgroup) only when no component covers the centroid, and a
-// frame whose pick is not its largest component gets its sums, box and hand
-// bits recomputed. Thread 0 then debounces the click and writes the pointer.
+// holds the largest component's pointer and root). Frame j's pick depends on
+// frame j - 1's centroid, so it is settled in order, but nearly all of the
+// work is done for all frames at once, on the guess that every earlier frame
+// kept its largest component:
+//   1. thread j stages frame j's pointer and largest root in LDS and tests
+//      whether frame j - 1's guessed centroid pixel lies in a component of
+//      frame j (the covering test: a few dependent loads);
+//   2. thread 0 walks the frames in order over LDS alone: a frame whose
+//      predecessor's actual centroid is the guess takes the test's answer
+//      (otherwise thread 0 tests again), and when its pick is its largest
+//      component its pointer only needs the debounced click. A frame that
+//      needs the whole workgroup - the nearest-component pass (nothing covers
+//      the centroid), or new sums, box and hand bits (the pick is not the
+//      largest) - stops the walk; the workgroup does that frame, and the
+//      walk goes on after it;
+//   3. thread j writes frame j's pointer; thread 0 the stream's state.
 constexpr int kChainMax = kMaxJobs;
 
 __global__ __launch_bounds__(kResolveThreads) void k_track_chain(Table *__restrict__ T)
 {
+    __shared__ fizi_pointer s_ptr[kChainMax];
     __shared__ uint32_t s_cover[kChainMax];
     __shared__ int32_t s_gx[kChainMax], s_gy[kChainMax];   // guessed previous centroid, -1: no hand
-    __shared__ int32_t s_ax, s_ay;                        // actual previous centroid, -1: no hand
-    __shared__ uint32_t s_near;
+    __shared__ int32_t s_ax, s_ay;                          // actual previous centroid, -1: no hand
+    __shared__ int s_next;                                  // frame the workgroup works on, or nj
+    __shared__ uint32_t s_pick;
+    __shared__ int s_zone;                                  // the frame needs its zone's sums recomputed
+    __shared__ uint32_t s_state;                            // debouncer state
     const int nj = min(T->h.njobs, kChainMax);
     if (nj == 0)
         return;
     TrackState *ts = T->jobs[0].track;
+    for (int j = threadIdx.x; j < nj; j += blockDim.x)
+        s_ptr[j] = *T->jobs[j].out;
+    __syncthreads();
+    // 1: the covering tests on the guess
     for (int j = threadIdx.x; j < nj; j += blockDim.x) {
         const Job *J = &T->jobs[j];
         int gx = -1, gy = -1;
@@ -1919,12 +1933,9 @@ __global__ __launch_bounds__(kResolveThreads) void k_track_chain(Table *__restri
                 gx = ts->x;
                 gy = ts->y;
             }
-        } else {
-            const fizi_pointer *p = T->jobs[j - 1].out;
-            if (p->present) {
-                gx = (int32_t)(p->sum_x / p->area);
-                gy = (int32_t)(p->sum_y / p->area);
-            }
+        } else if (s_ptr[j - 1].present) {
+            gx = (int32_t)(s_ptr[j - 1].sum_x / s_ptr[j - 1].area);
+            gy = (int32_t)(s_ptr[j - 1].sum_y / s_ptr[j - 1].area);
         }
         s_gx[j] = gx;
         s_gy[j] = gy;
@@ -1933,28 +1944,46 @@ __global__ __launch_bounds__(kResolveThreads) void k_track_chain(Table *__restri
     if (threadIdx.x == 0) {
         s_ax = ts->valid ? ts->x : -1;
         s_ay = ts->valid ? ts->y : -1;
+        s_state = ts->click;
     }
     __syncthreads();
-    for (int j = 0; j < nj; ++j) {
-        Job *J = &T->jobs[j];
-        const uint32_t amin = (uint32_t)max(J->min_area, 0);
-        const int ax = s_ax, ay = s_ay;
+    // 2: the frames in order
+    int j0 = 0;
+    for (;;) {
         if (threadIdx.x == 0) {
-            uint32_t c = s_cover[j];
-            if (ax != s_gx[j] || ay != s_gy[j])
-                c = ax >= 0 ? covering_root(J, ax, ay, amin) : kNoRoot;
-            s_near = c;
+            int j = j0;
+            for (; j < nj; ++j) {
+                const Job *J = &T->jobs[j];
+                const int ax = s_ax, ay = s_ay;
+                uint32_t c = s_cover[j];
+                if (ax != s_gx[j] || ay != s_gy[j])
+                    c = ax >= 0 ? covering_root(J, ax, ay, (uint32_t)max(J->min_area, 0)) : kNoRoot;
+                const bool near = ax >= 0 && c == kNoRoot && J->track_r2 > 0;
+                if (near || (c != kNoRoot && c != J->pick)) {
+                    s_pick = c;
+                    s_zone = !near;
+                    break;
+                }
+                // the largest component keeps the hand: only the click changes
+                fizi_pointer &o = s_ptr[j];
+                o.click = debounce_click(&s_state, o.present != 0, o.click, J->debounce);
+                s_ax = o.present ? (int32_t)(o.sum_x / o.area) : -1;
+                s_ay = o.present ? (int32_t)(o.sum_y / o.area) : -1;
+            }
+            s_next = j;
         }
         __syncthreads();
-        uint32_t pick = s_near;
-        __syncthreads();
-        if (ax >= 0 && pick == kNoRoot && J->track_r2 > 0)
-            pick = nearest_root(J, ax, ay, amin, J->track_r2);
-        const uint32_t largest = J->pick;
-        GLOBAL uint64_t *hand = J->hand ? G(J->hand) : nullptr;
-        fizi_pointer o = *J->out;
-        if (pick != kNoRoot && pick != largest) {
+        const int j = s_next;
+        if (j >= nj)
+            break;
+        Job *J = &T->jobs[j];
+        const uint32_t amin = (uint32_t)max(J->min_area, 0);
+        uint32_t pick = s_pick;
+        if (!s_zone)
+            pick = nearest_root(J, s_ax, s_ay, amin, J->track_r2);
+        if (pick != kNoRoot && pick != J->pick) {
             // the tracked zone is not the largest: its own sums, box, hand bits
+            GLOBAL uint64_t *hand = J->hand ? G(J->hand) : nullptr;
             if (hand) {
                 for (int i = threadIdx.x; i < J->H * J->Wd; i += blockDim.x)
                     hand[i] = 0ull;
@@ -1963,18 +1992,22 @@ __global__ __launch_bounds__(kResolveThreads) void k_track_chain(Table *__restri
             const uint32_t A = ld_wg(G(J->area) + pick);
             const ZoneStats z = zone_stats(J, pick, hand);
             if (threadIdx.x == 0)
-                o = make_pointer(J, true, A, z, o.n_components, o.inv_gain_q16);
+                s_ptr[j] = make_pointer(J, true, A, z, s_ptr[j].n_components, s_ptr[j].inv_gain_q16);
         }
         if (threadIdx.x == 0) {
-            const bool present = o.present != 0;
-            o.click = debounce_click(&ts->click, present, o.click, J->debounce);
-            *J->out = o;
-            s_ax = present ? (int32_t)(o.sum_x / o.area) : -1;
-            s_ay = present ? (int32_t)(o.sum_y / o.area) : -1;
+            fizi_pointer &o = s_ptr[j];
+            o.click = debounce_click(&s_state, o.present != 0, o.click, J->debounce);
+            s_ax = o.present ? (int32_t)(o.sum_x / o.area) : -1;
+            s_ay = o.present ? (int32_t)(o.sum_y / o.area) : -1;
         }
+        j0 = j + 1;
         __syncthreads();
     }
+    // 3: the pointers and the stream's state
+    for (int j = threadIdx.x; j < nj; j += blockDim.x)
+        *T->jobs[j].out = s_ptr[j];
     if (threadIdx.x == 0) {
+        ts->click = s_state;
         ts->valid = s_ax >= 0 ? 1 : 0;
         if (s_ax >= 0) {
             ts->x = s_ax;
