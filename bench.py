@@ -419,17 +419,33 @@ def cpu_baseline(args, scene, w):
     small_s = time.perf_counter() - t0
     small_px = sp0.width * sp0.height * (sp0.n_bg + sp0.n_hand)
 
-    # one thread: the 1920x1080 stream, first frames
+    # the 1920x1080 stream: one thread on its first frames, then all host
+    # threads on more of them (one frame per thread at a time; a frame's
+    # result does not depend on the others without tracking)
     sp1 = scene.hd_plain()
     sc1 = scene.Scene(sp1, device="cuda:0")
     m1 = oracle.Model(sp1.width, sp1.height)
     m1.learn(sc1.bg_frames(0, sp1.n_bg).cpu().numpy())
-    hand1 = sc1.hand_frames(0, args.cpu_hd_frames).cpu().numpy()
+    hand1 = sc1.hand_frames(0, max(args.cpu_hd_frames, args.cpu_hd_all_frames)).cpu().numpy()
     t0 = time.perf_counter()
-    for k in range(hand1.shape[0]):
+    for k in range(args.cpu_hd_frames):
         m1.process(hand1[k], frame_index=k)
     hd_s = time.perf_counter() - t0
-    hd_px = sp1.width * sp1.height * hand1.shape[0]
+    hd_px = sp1.width * sp1.height * args.cpu_hd_frames
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(nthr) as pool:
+        list(pool.map(lambda k: m1.process(hand1[k], frame_index=k), range(args.cpu_hd_all_frames)))
+    hd_all_s = time.perf_counter() - t0
+
+    # the soft mask's FP64 gradient (fused BCE) on 8 of the 32 calibration
+    # frames, scaled to the 32
+    from oracle import soft as osoft
+    f3, gt3 = scene.Scene(scene.calibration()).hand_frames(0, 8, with_gt=True)
+    f3, gt3 = f3.numpy(), gt3.numpy().astype(np.uint8)
+    t0 = time.perf_counter()
+    osoft.grad_bce(f3, gt3, osoft.CHECK_POINT, 0.5)
+    osoft.bce_loss(f3, gt3, osoft.CHECK_POINT, 0.5)
+    soft_s = time.perf_counter() - t0
     return {"value": round(all_px / all_s / 1e6, 2), "unit": "Mpixel/s", "cores": nthr, "kind": "oracle",
             "sample": f"batched workload: all {n} streams x {args.cpu_steps} frame steps "
                       f"({all_px / 1e6:.0f} Mpx) on {nthr} host threads, one stream per thread at a time, "
@@ -441,10 +457,16 @@ def cpu_baseline(args, scene, w):
                                  "Mpixel_per_s": round(small_px / small_s / 1e6, 2),
                                  "frames_per_s": round((sp0.n_bg + sp0.n_hand) / small_s, 1),
                                  "note": "30 learning + 100 hand frames, learning included"},
-                "1920x1080": {"frames": int(hand1.shape[0]), "seconds": round(hd_s, 3),
+                "1920x1080": {"frames": args.cpu_hd_frames, "seconds": round(hd_s, 3),
                               "Mpixel_per_s": round(hd_px / hd_s / 1e6, 2),
-                              "frames_per_s": round(hand1.shape[0] / hd_s, 2),
-                              "note": f"the first {hand1.shape[0]} of the stream's 2000 hand frames"}}}
+                              "frames_per_s": round(args.cpu_hd_frames / hd_s, 2),
+                              "note": f"the first {args.cpu_hd_frames} of the stream's 2000 hand frames"},
+                "soft_fp64_gradient_32x1280x720_s": round(soft_s * 4, 3)},
+            "all_threads_1920x1080": {"frames": args.cpu_hd_all_frames, "threads": nthr,
+                                      "seconds": round(hd_all_s, 3),
+                                      "frames_per_s": round(args.cpu_hd_all_frames / hd_all_s, 2),
+                                      "Mpixel_per_s": round(sp1.width * sp1.height * args.cpu_hd_all_frames
+                                                            / hd_all_s / 1e6, 2)}}
 
 
 def main():
@@ -458,6 +480,8 @@ def main():
     ap.add_argument("--latency-frames", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=10, help="frame steps of the batched workload on the CPU")
     ap.add_argument("--cpu-hd-frames", type=int, default=60, help="1920x1080 frames on one CPU thread")
+    ap.add_argument("--cpu-hd-all-frames", type=int, default=256,
+                    help="1920x1080 frames on all host threads, one frame per thread")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
