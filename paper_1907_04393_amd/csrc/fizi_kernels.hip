@@ -651,30 +651,29 @@ __device__ __forceinline__ void classify_tile(Table *__restrict__ T, int j, int 
     }
 }
 
-// Per block, once: the tile prefix and every frame's inverse gain in LDS, so
-// a tile costs neither a search nor a division.
-__device__ __forceinline__ void stage_jobs(Table *__restrict__ T, int nj, int32_t *s_pre, uint32_t *s_inv,
-                                           bool same_launch)
-{
-    for (int i = threadIdx.x; i <= nj; i += blockDim.x)
-        s_pre[i] = T->h.cls_pre[i];
-    for (int i = threadIdx.x; i < nj; i += blockDim.x)
-        s_inv[i] = job_gain(&T->jobs[i], same_launch);
-    __syncthreads();
-}
-
 // Tiles blockIdx.x, blockIdx.x + gridDim.x, ...: the frame index only grows,
-// so it is advanced, not searched.
+// so it is advanced, not searched. A block meets one to three frames, so a
+// frame's inverse gain (sixteen pairs of sums and a 64-bit division) is
+// computed when its first tile comes, once per block, by thread 0.
 template <int ITERS>
-__device__ __forceinline__ void classify_tiles(Table *__restrict__ T, int nj, const int32_t *s_pre,
-                                               const uint32_t *s_inv)
+__device__ __forceinline__ void classify_tiles(Table *__restrict__ T, int nj, const int32_t *s_pre)
 {
+    __shared__ uint32_t s_inv;
     const int total = s_pre[nj];
-    int j = 0;
+    int j = 0, jinv = -1;
+    uint32_t inv = 0;
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         while (s_pre[j + 1] <= t)
             ++j;
-        classify_tile<ITERS>(T, j, t - s_pre[j], s_inv[j]);
+        if (j != jinv) {
+            __syncthreads();
+            if (threadIdx.x == 0)
+                s_inv = job_gain(&T->jobs[j], false);
+            __syncthreads();
+            inv = s_inv;
+            jinv = j;
+        }
+        classify_tile<ITERS>(T, j, t - s_pre[j], inv);
     }
 }
 
@@ -682,10 +681,11 @@ template <int ITERS>
 __global__ __launch_bounds__(256) void k_classify(Table *__restrict__ T)
 {
     __shared__ int32_t s_pre[kMaxJobs + 1];
-    __shared__ uint32_t s_inv[kMaxJobs];
     const int nj = T->h.njobs;
-    stage_jobs(T, nj, s_pre, s_inv, false);
-    classify_tiles<ITERS>(T, nj, s_pre, s_inv);
+    for (int i = threadIdx.x; i <= nj; i += blockDim.x)
+        s_pre[i] = T->h.cls_pre[i];
+    __syncthreads();
+    classify_tiles<ITERS>(T, nj, s_pre);
 }
 
 // ---------------------------------------------------------------------------
