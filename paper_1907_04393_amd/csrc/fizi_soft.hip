@@ -18,33 +18,36 @@ constexpr int kSoftOut = 8;        // 6 gradients, loss, unused
 constexpr int kSoftU = 4;          // pixel groups per thread and iteration of the adjoint
 
 struct SoftParams {
-    float mu_b, mu_r;
+    float kb, kr;                  // 128 - mu_b, 128 - mu_r: chroma offset less the mean
     float p_bb, p_br, p_rr;        // inverse covariance
-    float theta, inv_t;
+    float z0, z1;                  // z log2(e) = z0 - z1 d: theta / T and 1 / T, times log2(e)
 };
 
+// z is kept in base-2 units (z log2 e), so that the exponential and the
+// logarithm are single hardware instructions with no scaling; rs = 1 / d;
+// e = exp(-|z|).
 struct SoftPx {
-    float m, z, d, h, e, ub, ur;   // h = 1 / (2 d) (0 at d = 0), e = exp(-|z|)
+    float m, z, rs, e, ub, ur;
 };
 
 // Three transcendentals per pixel, each one hardware instruction (about one
 // ulp, far inside the relative 1e-4 the calibration form needs): one
-// reciprocal square root gives d and 1 / (2 d), one exponential gives the
-// sigmoid (and the BCE's softplus), one reciprocal.
+// reciprocal square root gives d and 1 / d, one exponential gives the
+// sigmoid (and the BCE's softplus), one reciprocal. q is a positive
+// definite form: 0 only where the pixel's chroma is the mean (u = 0, so
+// every gradient term is 0 whatever rs), and it is held at FLT_MIN there so
+// that d = sqrt(q) stays finite (about 1e-19).
 __device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftParams &s)
 {
-    const float cb = fmaf(0.5f, b, fmaf(-0.331264f, g, fmaf(-0.168736f, r, 128.0f)));
-    const float cr = fmaf(-0.081312f, b, fmaf(-0.418688f, g, fmaf(0.5f, r, 128.0f)));
-    const float db = cb - s.mu_b, dr = cr - s.mu_r;
+    const float db = fmaf(0.5f, b, fmaf(-0.331264f, g, fmaf(-0.168736f, r, s.kb)));
+    const float dr = fmaf(-0.081312f, b, fmaf(-0.418688f, g, fmaf(0.5f, r, s.kr)));
     SoftPx o;
     o.ub = fmaf(s.p_bb, db, s.p_br * dr);
     o.ur = fmaf(s.p_br, db, s.p_rr * dr);
-    const float q = fmaxf(fmaf(db, o.ub, dr * o.ur), 0.0f);
-    const float rs = q > 0.0f ? __builtin_amdgcn_rsqf(q) : 0.0f;
-    o.d = q * rs;
-    o.h = 0.5f * rs;
-    o.z = (s.theta - o.d) * s.inv_t;
-    o.e = __expf(-fabsf(o.z));
+    const float q = fmaxf(fmaf(db, o.ub, dr * o.ur), 1.17549435e-38f);
+    o.rs = __builtin_amdgcn_rsqf(q);
+    o.z = fmaf(-s.z1, q * o.rs, s.z0);
+    o.e = __builtin_amdgcn_exp2f(-fabsf(o.z));
     const float rc = __builtin_amdgcn_rcpf(1.0f + o.e);
     o.m = o.z >= 0.0f ? rc : o.e * rc;
     return o;
@@ -77,13 +80,15 @@ __global__ __launch_bounds__(256) void k_soft_fwd(const uint8_t *__restrict__ fr
     }
 }
 
-// Adds one pixel's contributions (FP32) to acc: dL/dz is gz. With
-// g = -dL/dq = gz / (2 T d) and u = S^-1 delta: dL/dmu = 2 g u, dL/dS =
-// g u u^T (the off-diagonal entry counted twice) and dL/dtheta = gz / T; the
-// constant factors (2, 2, 1, 2, 1, 1/T) are applied once, to the final sums.
-__device__ __forceinline__ void soft_acc(const SoftPx &o, float gz, float inv_t, float *acc)
+// Adds one pixel's contributions (FP32) to acc, gz being dL/dz up to a
+// constant factor c. With u = S^-1 delta: dL/dmu = (gz / (T d)) u, dL/dS =
+// (gz / (2 T d)) u u^T (the off-diagonal entry counted twice) and dL/dtheta
+// = gz / T; the sums carry gz / d = gz rs and gz, and the constant factors
+// (c / T, c / T, c / 2T, c / T, c / 2T, c / T) are applied once, to the final
+// sums.
+__device__ __forceinline__ void soft_acc(const SoftPx &o, float gz, float *acc)
 {
-    const float gq = gz * inv_t * o.h;     // -dL/dq
+    const float gq = gz * o.rs;
     const float a = gq * o.ub, b = gq * o.ur;
     acc[0] += a;
     acc[1] += b;
@@ -93,29 +98,31 @@ __device__ __forceinline__ void soft_acc(const SoftPx &o, float gz, float inv_t,
     acc[5] += gz;
 }
 
-// dL/dz of one pixel from the upstream dL/dm.
-__device__ __forceinline__ float gz_upstream(const SoftPx &o, float dm) { return dm * o.m * (1.0f - o.m); }
+// dL/dz of one pixel from the upstream dL/dm (c = 1).
+__device__ __forceinline__ float gz_upstream(const SoftPx &o, float dm) { return dm * fmaf(-o.m, o.m, o.m); }
 
-// Fused BCE: dL/dz = (m - y) / N, and the pixel's BCE term is added to acc[6].
-__device__ __forceinline__ float gz_bce(const SoftPx &o, uint32_t y8, float inv_n, float *acc)
+// Fused BCE: dL/dz = (m - y) / N (c = 1 / N, applied to the sums), and the
+// pixel's BCE term in base-2 units, max(z, 0) - z y + log2(1 + e), is added
+// to acc[6] (times ln 2 / N at the end).
+__device__ __forceinline__ float gz_bce(const SoftPx &o, uint32_t y8, float *acc)
 {
-    const float y = y8 ? 1.0f : 0.0f;
-    acc[6] += fmaxf(o.z, 0.0f) - o.z * y + __logf(1.0f + o.e);
-    return (o.m - y) * inv_n;
+    const float y = fminf((float)y8, 1.0f);
+    acc[6] += fmaf(-o.z, y, fmaxf(o.z, 0.0f)) + __builtin_amdgcn_logf(1.0f + o.e);
+    return o.m - y;
 }
 
 // One group of 4 pixels (3 frame dwords) with its upstream gradients (dm) or
 // ground-truth bytes (y4), added to acc in FP32.
 template <bool BCE>
 __device__ __forceinline__ void soft_group(uint32_t w0, uint32_t w1, uint32_t w2, const float *dm, uint32_t y4,
-                                           const SoftParams &s, float inv_n, float *acc)
+                                           const SoftParams &s, float *acc)
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const SoftPx o = soft_px(byte_at(w0, w1, w2, 3 * k), byte_at(w0, w1, w2, 3 * k + 1),
                                  byte_at(w0, w1, w2, 3 * k + 2), s);
-        const float gz = BCE ? gz_bce(o, (y4 >> (8 * k)) & 0xFFu, inv_n, acc) : gz_upstream(o, dm[k]);
-        soft_acc(o, gz, s.inv_t, acc);
+        const float gz = BCE ? gz_bce(o, (y4 >> (8 * k)) & 0xFFu, acc) : gz_upstream(o, dm[k]);
+        soft_acc(o, gz, acc);
     }
 }
 
@@ -124,7 +131,7 @@ __device__ __forceinline__ void soft_group(uint32_t w0, uint32_t w1, uint32_t w2
 template <bool BCE, bool VEC>
 __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ frames, const float *__restrict__ dLdm,
                                                   const uint8_t *__restrict__ gt, long long npx, SoftParams s,
-                                                  float inv_n, double *__restrict__ partial)
+                                                  double *__restrict__ partial)
 {
     __shared__ double s_red[256 / 64][kSoftOut];
     double acc[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -172,7 +179,7 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ fr
 #pragma unroll
         for (int u = 0; u < kSoftU; ++u)
             if (have[u])
-                soft_group<BCE>(w[u][0], w[u][1], w[u][2], dm[u], y4[u], s, inv_n, a8);
+                soft_group<BCE>(w[u][0], w[u][1], w[u][2], dm[u], y4[u], s, a8);
 #pragma unroll
         for (int k = 0; k < kSoftOut - 1; ++k)
             acc[k] += (double)a8[k];
@@ -181,8 +188,8 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ fr
         const long long i = 4 * groups + threadIdx.x;
         float a1[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};
         const SoftPx o = soft_px(frames[3 * i], frames[3 * i + 1], frames[3 * i + 2], s);
-        const float gz = BCE ? gz_bce(o, gt[i], inv_n, a1) : gz_upstream(o, dLdm[i]);
-        soft_acc(o, gz, s.inv_t, a1);
+        const float gz = BCE ? gz_bce(o, gt[i], a1) : gz_upstream(o, dLdm[i]);
+        soft_acc(o, gz, a1);
         for (int k = 0; k < kSoftOut - 1; ++k)
             acc[k] += (double)a1[k];
     }
@@ -240,13 +247,14 @@ int soft_params(const float p6[6], float T, SoftParams *s)
         return fail(FIZI_EINVAL, "covariance must be positive definite");
     if (!(T > 0.0f) || !std::isfinite(T))
         return fail(FIZI_EINVAL, "temperature must be positive");
-    s->mu_b = p6[0];
-    s->mu_r = p6[1];
+    const double log2e = 1.4426950408889634, inv_t = 1.0 / (double)T;
+    s->kb = (float)(128.0 - (double)p6[0]);
+    s->kr = (float)(128.0 - (double)p6[1]);
     s->p_bb = (float)(srr / det);
     s->p_br = (float)(-sbr / det);
     s->p_rr = (float)(sbb / det);
-    s->theta = p6[5];
-    s->inv_t = 1.0f / T;
+    s->z0 = (float)((double)p6[5] * inv_t * log2e);
+    s->z1 = (float)(inv_t * log2e);
     return FIZI_OK;
 }
 
@@ -286,23 +294,24 @@ int soft_backward(const uint8_t *frames, const float *dLdm, const uint8_t *gt, l
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int grid = soft_grid(npx);
     double *partial = static_cast<double *>(ws);
-    const float inv_n = (float)(1.0 / (double)npx);
     const StageEvents ev = soft_ev(FIZI_SOFT_STAGE_BACKWARD);
     if (gt) {
         if (reinterpret_cast<uintptr_t>(gt) % 4 == 0)
-            FIZI_LAUNCH((k_soft_bwd<true, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, inv_n, partial);
+            FIZI_LAUNCH((k_soft_bwd<true, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, partial);
         else
-            FIZI_LAUNCH((k_soft_bwd<true, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, inv_n, partial);
+            FIZI_LAUNCH((k_soft_bwd<true, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, partial);
     } else {
         if (reinterpret_cast<uintptr_t>(dLdm) % 16 == 0)
-            FIZI_LAUNCH((k_soft_bwd<false, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, inv_n, partial);
+            FIZI_LAUNCH((k_soft_bwd<false, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, partial);
         else
-            FIZI_LAUNCH((k_soft_bwd<false, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, inv_n,
-                        partial);
+            FIZI_LAUNCH((k_soft_bwd<false, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, partial);
     }
     FIZI_HIP(hipGetLastError());
-    // dL/dmu_b, dL/dmu_r, dL/ds_bb, dL/ds_br, dL/ds_rr, dL/dtheta, loss
-    const SoftScale scale{{2.0, 2.0, 1.0, 2.0, 1.0, (double)s.inv_t, 1.0 / (double)npx, 0.0}};
+    // dL/dmu_b, dL/dmu_r, dL/ds_bb, dL/ds_br, dL/ds_rr, dL/dtheta, loss: the
+    // constant factors the kernel leaves out (c = 1 / N for the BCE, 1 for
+    // an upstream dL/dm; the loss sum is in base-2 units)
+    const double c = gt ? 1.0 / (double)npx : 1.0, ct = c / (double)T;
+    const SoftScale scale{{ct, ct, 0.5 * ct, ct, 0.5 * ct, ct, c * 0.69314718055994531, 0.0}};
     const StageEvents ev_final = soft_ev(FIZI_SOFT_STAGE_FINAL);
     FIZI_LAUNCH(k_soft_final, nout, 256, 0, st, ev_final, partial, grid, scale, out);
     FIZI_HIP(hipGetLastError());
