@@ -330,13 +330,13 @@ int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_para
     if (rc == FIZI_OK) {
         hipError_t e = hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming);
         if (e == hipSuccess)
-            e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
+            e = hipEventCreateWithFlags(&b->fork_ev, kDeviceOrderEvent);
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {
             e = hipEventCreateWithFlags(&b->up_ev[k], hipEventDisableTiming);
             if (e == hipSuccess)
-                e = hipEventCreateWithFlags(&b->cls_ev[k], hipEventDisableTiming);
+                e = hipEventCreateWithFlags(&b->cls_ev[k], kDeviceOrderEvent);
             if (e == hipSuccess)
-                e = hipEventCreateWithFlags(&b->join_ev[k], hipEventDisableTiming);
+                e = hipEventCreateWithFlags(&b->join_ev[k], kDeviceOrderEvent);
         }
         if (e == hipSuccess)
             e = (hipError_t)launch_fill_u32(reinterpret_cast<uint32_t *>(b->persist), 0u,

@@ -194,9 +194,9 @@ int fizi_create(const fizi_geom *geom, const fizi_params *params, int32_t chunk_
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {
             e = hipEventCreateWithFlags(&c->up_ev[k], hipEventDisableTiming);
             if (e == hipSuccess)
-                e = hipEventCreateWithFlags(&c->cls_ev[k], hipEventDisableTiming);
+                e = hipEventCreateWithFlags(&c->cls_ev[k], kDeviceOrderEvent);
             if (e == hipSuccess)
-                e = hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming);
+                e = hipEventCreateWithFlags(&c->join_ev[k], kDeviceOrderEvent);
         }
         if (e == hipSuccess)
             e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);

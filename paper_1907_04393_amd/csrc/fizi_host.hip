@@ -279,7 +279,8 @@ int TableRing::init(uint8_t *d_base)
         d[i] = reinterpret_cast<Table *>(d_base + i * align256(sizeof(Table)));
         FIZI_HIP(hipHostMalloc(reinterpret_cast<void **>(&h[i]), sizeof(Table), hipHostMallocDefault));
         std::memset(h[i], 0, sizeof(Table));
-        FIZI_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+        // the host only waits for the slot's kernels to be done with it
+        FIZI_HIP(hipEventCreateWithFlags(&ev[i], kDeviceOrderEvent));
     }
     return FIZI_OK;
 }
