@@ -34,9 +34,11 @@ struct SoftPx {
 // ulp, far inside the relative 1e-4 the calibration form needs): one
 // reciprocal square root gives d and 1 / d, one exponential gives the
 // sigmoid (and the BCE's softplus), one reciprocal. q is a positive
-// definite form: 0 only where the pixel's chroma is the mean (u = 0, so
-// every gradient term is 0 whatever rs), and it is held at FLT_MIN there so
-// that d = sqrt(q) stays finite (about 1e-19).
+// definite form, 0 only where the pixel's chroma is the mean (u = 0, so
+// every gradient term is 0 whatever rs); it is held at 2^-100 there, so
+// that rs = 2^50 and d = 2^-50 stay finite (the reading d = 0, up to a z
+// change far below FP32 resolution). A q that small otherwise needs a
+// covariance eigenvalue below 1e-20.
 __device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftParams &s)
 {
     const float db = fmaf(0.5f, b, fmaf(-0.331264f, g, fmaf(-0.168736f, r, s.kb)));
@@ -44,7 +46,7 @@ __device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftP
     SoftPx o;
     o.ub = fmaf(s.p_bb, db, s.p_br * dr);
     o.ur = fmaf(s.p_br, db, s.p_rr * dr);
-    const float q = fmaxf(fmaf(db, o.ub, dr * o.ur), 1.17549435e-38f);
+    const float q = fmaxf(fmaf(db, o.ub, dr * o.ur), 0x1p-100f);
     o.rs = __builtin_amdgcn_rsqf(q);
     o.z = fmaf(-s.z1, q * o.rs, s.z0);
     o.e = __builtin_amdgcn_exp2f(-fabsf(o.z));

@@ -51,6 +51,36 @@ def test_forward_and_adjoint_small(p, T):
 
 
 @pytest.mark.parametrize("T", [0.5, 2.0])
+def test_zero_distance_pixels(T):
+    """Black pixels sit exactly at mu = (128, 128) with S = I, in FP32 as in
+    FP64: d = 0, m = sigmoid(theta / T) in closed form, and they add nothing
+    to the mean and covariance gradients (the reading at d = 0); mixed with
+    generic pixels, the whole gradient still matches the FP64 oracle."""
+    from oracle import soft as osoft
+    from paper_1907_04393_amd import soft
+    dev = need_gpu()
+    f, _ = _calib(1)
+    black = torch.zeros((1000, 3), dtype=torch.uint8)
+    flat = torch.cat([black, f[0, :64].reshape(-1, 3), black[:3]]).contiguous()
+    p = (128.0, 128.0, 1.0, 0.0, 1.0, 1.3)
+    prm = torch.tensor(p, dtype=torch.float64)
+    closed = 1.0 / (1.0 + np.exp(-1.3 / T))
+    m = soft.soft_forward(flat.to(dev), prm, T).cpu().numpy().astype(np.float64)
+    ref = osoft.mask(flat.numpy(), p, T)
+    assert np.abs(m[:1000] - closed).max() < 2e-5
+    assert np.abs(m - ref).max() < 2e-5
+    rng = np.random.default_rng(7)
+    dLdm = rng.normal(size=ref.size).astype(np.float32)
+    g = soft.soft_backward(flat.to(dev), torch.from_numpy(dLdm).to(dev), prm, T).cpu().numpy()
+    ok, rel = _close(g, osoft.grad_from_dm(flat.numpy(), dLdm.astype(np.float64), p, T))
+    assert ok, rel
+    g0 = soft.soft_backward(black.to(dev), torch.from_numpy(dLdm[:1000]).to(dev), prm, T).cpu().numpy()
+    assert np.all(g0[:5] == 0.0)
+    dth = float(np.sum(dLdm[:1000].astype(np.float64)) * closed * (1.0 - closed) / T)
+    assert abs(g0[5] - dth) <= 1e-4 * abs(dth)
+
+
+@pytest.mark.parametrize("T", [0.5, 2.0])
 def test_calibration_workload_full_size(T):
     """32 frames 1280x720 with ground-truth hand masks: the fused BCE pass and
     the autograd path (soft mask, torch BCE, hand-written backward) both
