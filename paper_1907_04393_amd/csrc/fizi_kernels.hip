@@ -9,7 +9,7 @@
 //                and written once (Section 3.1 (i), Section 3.3)
 //   k_classify   gain correction (or thresholds scaled by the gain), I_R1
 //                (outside the learned box), I_R2 (not gray), I_R3 (skin hue),
-//                their AND, packed to bits with wave ballots (Sections 3.1,
+//                their AND, packed to bits by DPP row merges (Sections 3.1,
 //                3.2); HBM-bound, 4 pixels per lane
 //   k_morph      opening then closing with a 3x3 square, streamed through a
 //                register pipeline of bit rows (64 pixels per lane word), then
@@ -200,15 +200,27 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-// Spreads the low 16 bits of x so that bit t lands on bit 4t.
-__device__ __forceinline__ uint64_t spread4(uint64_t x)
+// Lane l receives lane l + n of its row of 16 lanes (0 past the row's end):
+// DPP row_shl:n.
+template <int N>
+__device__ __forceinline__ uint32_t row_shl(uint32_t v)
 {
-    x &= 0xFFFFull;
-    x = (x | (x << 24)) & 0x000000FF000000FFull;
-    x = (x | (x << 12)) & 0x000F000F000F000Full;
-    x = (x | (x << 6)) & 0x0303030303030303ull;
-    x = (x | (x << 3)) & 0x1111111111111111ull;
-    return x;
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + N, 0xF, 0xF, false);
+}
+
+// Raster mask words of a wave's 256 consecutive pixels, 4 per lane (bit k of
+// nib: pixel 4 l + k). Word w covers lanes 16 w .. 16 w + 15, nibble j from
+// lane 16 w + j, so each word is one DPP row: neighbouring lanes' nibbles
+// merge pairwise (l takes l + 1, then l + 2, l + 4; l + 8 gives the upper
+// half), and lane 16 w ends up holding word w. A handful of instructions per
+// wave, where ballots and a bit spread on four lanes took about eighty.
+__device__ __forceinline__ uint64_t row_word(uint32_t nib)
+{
+    uint32_t t = nib & 0xFu;
+    t |= row_shl<1>(t) << 4;
+    t |= row_shl<2>(t) << 8;
+    t |= row_shl<4>(t) << 16;
+    return ((uint64_t)row_shl<8>(t) << 32) | t;
 }
 
 // ---------------------------------------------------------------------------
@@ -584,14 +596,11 @@ __device__ __forceinline__ void classify_px4(const ClsJob &c, uint32_t base, uin
             }
         }
     }
-    const uint64_t b0 = __ballot(bits & 1u), b1 = __ballot(bits & 2u),
-                   b2 = __ballot(bits & 4u), b3 = __ballot(bits & 8u);
-    if (lane < 4) {
-        const uint32_t word = (base >> 6) + lane;
-        const int sh = 16 * lane;
+    const uint64_t w = row_word(bits);
+    if ((lane & 15) == 0) {
+        const uint32_t word = (base >> 6) + (uint32_t)(lane >> 4);
         if (word < (pend >> 6))
-            put<FLOW>(c.raw + word, spread4(b0 >> sh) | (spread4(b1 >> sh) << 1) | (spread4(b2 >> sh) << 2) |
-                                        (spread4(b3 >> sh) << 3));
+            put<FLOW>(c.raw + word, w);
     }
 }
 
