@@ -200,12 +200,12 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-// Lane l receives lane l + n of its row of 16 lanes (0 past the row's end):
-// DPP row_shl:n.
+// Lane l receives lane l + n of its row of 16 lanes (0 past the row's end,
+// by the bound control): DPP row_shl:n.
 template <int N>
 __device__ __forceinline__ uint32_t row_shl(uint32_t v)
 {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + N, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + N, 0xF, 0xF, true);
 }
 
 // Raster mask words of a wave's 256 consecutive pixels, 4 per lane (bit k of
@@ -514,16 +514,28 @@ struct Px4 {
     uint32_t f[3], l[3], u[3];
 };
 
+// The byte offset (3 p < 2^28: frames are at most 8192 x 8192) is
+// added to each array's wave-uniform base as an unsigned 32-bit value, so
+// that the loads take the scalar-base, vector-offset form and no 64-bit
+// address is formed per lane.
+template <typename T>
+__device__ __forceinline__ const GLOBAL T *at_byte(const GLOBAL T *base, uint32_t off)
+{
+    return reinterpret_cast<const GLOBAL T *>(reinterpret_cast<const GLOBAL uint8_t *>(base) + off);
+}
+
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+
 __device__ __forceinline__ void load_px4(const ClsJob &c, uint32_t p, uint32_t pend, Px4 &x)
 {
     if (p < pend) {
-        const uint32_t q = 3u * (p >> 2);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            x.f[k] = __builtin_nontemporal_load(c.fr + q + k);
-            x.l[k] = __builtin_nontemporal_load(c.mn + q + k);
-            x.u[k] = __builtin_nontemporal_load(c.mx + q + k);
-        }
+        const uint32_t off = 3u * p;
+        const u32x3 f = __builtin_nontemporal_load(at_byte(reinterpret_cast<const GLOBAL u32x3 *>(c.fr), off));
+        const u32x3 l = __builtin_nontemporal_load(at_byte(reinterpret_cast<const GLOBAL u32x3 *>(c.mn), off));
+        const u32x3 u = __builtin_nontemporal_load(at_byte(reinterpret_cast<const GLOBAL u32x3 *>(c.mx), off));
+        x.f[0] = f.x, x.f[1] = f.y, x.f[2] = f.z;
+        x.l[0] = l.x, x.l[1] = l.y, x.l[2] = l.z;
+        x.u[0] = u.x, x.u[1] = u.y, x.u[2] = u.z;
     }
 }
 
