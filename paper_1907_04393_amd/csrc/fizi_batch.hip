@@ -328,7 +328,7 @@ int fizi_batch_create(int32_t n_streams, const fizi_geom *geoms, const fizi_para
     if (rc == FIZI_OK)
         rc = b->ring.init(b->d + L.tables);
     if (rc == FIZI_OK) {
-        hipError_t e = hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming);
+        hipError_t e = hipEventCreateWithFlags(&b->order_ev, kDeviceOrderEvent);
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&b->fork_ev, kDeviceOrderEvent);
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {

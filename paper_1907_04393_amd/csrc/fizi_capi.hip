@@ -54,9 +54,11 @@ struct fizi_ctx {
     TableRing ring;
     StageClock clk;
     fizi_pointer *h_ring = nullptr;
+    // frames [f0, f1) are in the host pointer ring once `ev` (recorded after
+    // their copy, default fences: the host reads what the copy wrote) is done
     struct Rec {
         uint64_t f0, f1;
-        int slot;
+        hipEvent_t ev;
         bool valid;
     } recs[kRecs] = {};
     int next_rec = 0;
@@ -190,7 +192,9 @@ int fizi_create(const fizi_geom *geom, const fizi_params *params, int32_t chunk_
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->h_ring), sizeof(fizi_pointer) * kRing,
                                      hipHostMallocDefault);
         if (e == hipSuccess)
-            e = hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming);
+            e = hipEventCreateWithFlags(&c->order_ev, kDeviceOrderEvent);
+        for (int i = 0; i < kRecs && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&c->recs[i].ev, hipEventDisableTiming);
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {
             e = hipEventCreateWithFlags(&c->up_ev[k], hipEventDisableTiming);
             if (e == hipSuccess)
@@ -325,7 +329,7 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
             c->next_rec = (c->next_rec + 1) % kRecs;
             r.f0 = fbase;
             r.f1 = fbase + k;
-            r.slot = slot;
+            FIZI_HIP(hipEventRecord(r.ev, bs));
             r.valid = true;
         }
         (void)last;
@@ -339,7 +343,7 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
         c->next_rec = (c->next_rec + 1) % kRecs;
         r.f0 = c->next_frame;
         r.f1 = c->next_frame + (uint64_t)n_frames;
-        r.slot = last_slot;
+        FIZI_HIP(hipEventRecord(r.ev, s));
         r.valid = true;
     }
     c->next_frame += (uint64_t)n_frames;
@@ -364,7 +368,7 @@ int get_pointer(fizi_ctx *c, int64_t frame_index, fizi_pointer *h_out)
     }
     if (best < 0)
         return fail(FIZI_ERANGE, "frame record missing");
-    FIZI_HIP(hipEventSynchronize(c->ring.ev[c->recs[best].slot]));
+    FIZI_HIP(hipEventSynchronize(c->recs[best].ev));
     *h_out = c->h_ring[(size_t)frame_index % kRing];
     return FIZI_OK;
 }
@@ -409,6 +413,9 @@ int fizi_destroy(fizi_ctx *c)
                          c->join_ev[1]})
         if (e)
             (void)hipEventDestroy(e);
+    for (const fizi_ctx::Rec &r : c->recs)
+        if (r.ev)
+            (void)hipEventDestroy(r.ev);
     for (hipStream_t st : {c->side, c->up})
         if (st)
             (void)hipStreamDestroy(st);

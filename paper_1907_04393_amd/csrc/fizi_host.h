@@ -101,10 +101,11 @@ struct TableRing {
 // Flags of the events that only order device work after other device work
 // on the same GPU (a kernel's outputs read by a kernel on another stream, a
 // buffer reused once the kernels reading it are done), or that the host
-// waits on for completion alone: no system-scope fence, which would write
-// back the caches for the host at every record. The kernels' own dispatch
-// fences make their writes visible to the device. An event that orders
-// kernels after a host-to-device copy keeps the default flags.
+// waits on for completion alone, reading nothing the device wrote to host
+// memory: no system-scope fence, which would write back the caches for the
+// host at every record. The kernels' own dispatch fences make their writes
+// visible to the device. An event that orders kernels after a host-to-device
+// copy, or host reads after a device-to-host copy, keeps the default flags.
 constexpr unsigned kDeviceOrderEvent = hipEventDisableTiming | hipEventDisableSystemFence;
 
 struct StageClock {
