@@ -340,10 +340,11 @@ int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t);
 
 /* Autotuner (the paper's Section 3.3 tunes its GPU memory use dynamically;
  * here the launch shapes are tuned on the caller's workload): times `steps`
- * frame steps of h_frames (as in fizi_batch_step, after two warm-up steps)
- * for each candidate of a coordinate sweep - mode, then cls_iters, then
- * grid_per_cu, then morph_rows - keeps the fastest, leaves it set, and
- * returns it with its milliseconds per step. Synchronous. */
+ * frame steps of h_frames twice (as in fizi_batch_step, after two warm-up
+ * steps) for each candidate of a coordinate sweep - mode, then cls_iters,
+ * then grid_per_cu, then morph_rows - keeps the fastest by the better of its
+ * two times, leaves it set, and returns it with its milliseconds per step.
+ * Synchronous. */
 int fizi_batch_autotune(fizi_batch *b, const uint8_t *const *h_frames, fizi_pointer *d_pointers,
                         int32_t steps, void *stream, fizi_tuning *best, double *best_ms);
 
