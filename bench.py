@@ -234,6 +234,7 @@ def bench_plain(args, torch, fizi, scene):
     return {"workload": "one 1920x1080 stream, frames processed in batches of "
                         f"{args.plain_batch} (internal launches of {scene.HD_CHUNK} frames)",
             "Mpixel_per_s": round(fps * W * H / 1e6, 1), "frames_per_s": round(fps, 1),
+            "path_roofline_frac": round(fps * W * H * PATH_BYTES_PER_PX / (HBM_PEAK_GBS * 1e9), 4),
             "tracking_frames_per_s": round(track_fps, 1),
             "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99),
                            "mode": "one frame per call, pointer read back on the host"}}
