@@ -280,8 +280,8 @@ __device__ __forceinline__ void gain_tile_mode(Table *__restrict__ T, int j, int
         // 16 pixels per item: three 16-byte loads of the frame row, two of
         // the reference row; items of the tile's rows in one flat range
         const int n16 = W / 16;
-        const uint8_t *frame = J->frame;
-        const uint16_t *yref = J->yref;
+        const GLOBAL uint8_t *frame = G(J->frame);
+        const GLOBAL uint16_t *yref = G(J->yref);
         const size_t rowb = (size_t)J->rs * W * 3;
 #pragma unroll 2
         for (int it = threadIdx.x; it < nr * n16; it += blockDim.x) {
@@ -290,8 +290,8 @@ __device__ __forceinline__ void gain_tile_mode(Table *__restrict__ T, int j, int
             for (int q = 1; q < kGainRows; ++q)
                 row += it >= q * n16;
             const int g = it - row * n16, rr = r0 + row;
-            const u32x4 *fp = reinterpret_cast<const u32x4 *>(frame + (size_t)rr * rowb) + 3 * g;
-            const u32x4 *yp = reinterpret_cast<const u32x4 *>(yref + (size_t)rr * W) + 2 * g;
+            const GLOBAL u32x4 *fp = reinterpret_cast<const GLOBAL u32x4 *>(frame + (size_t)rr * rowb) + 3 * g;
+            const GLOBAL u32x4 *yp = reinterpret_cast<const GLOBAL u32x4 *>(yref + (size_t)rr * W) + 2 * g;
             const u32x4 a = fp[0], b = fp[1], c = fp[2], ya = yp[0], yb = yp[1];
             const uint32_t fw[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
             const uint32_t yw[8] = {ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w};
