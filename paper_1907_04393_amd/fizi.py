@@ -344,6 +344,7 @@ class Batch:
         check(L.fizi_batch_create(self.n, self._g, self._p, _ptr(self.state), nbytes, ctypes.byref(self._h)))
         self._frames = (ctypes.c_void_p * self.n)()
         self._fizi = (ctypes.c_void_p * self.n)()
+        self._shapes = [(h, w, 3) for w, h in self.geoms]
         # the last step's output tensors: in the pipelined modes they are
         # written by the next step or flush(), so they are kept alive until then
         self._held = None
@@ -382,17 +383,24 @@ class Batch:
 
     def _check_step(self, frames, pointers, fizi):
         """The library sees only device addresses: every argument of a step
-        is checked against the batch's geometry here, before any is passed."""
+        is checked against the batch's geometry here, before any is passed.
+        Returns the frame address array, every entry set (NULL when idle).
+        One pass per frame with cheap attribute tests: a step's host time is
+        part of its latency."""
         if len(frames) != self.n:
             raise FiziError(FIZI_EINVAL, f"a step takes {self.n} frame entries, got {len(frames)}")
+        arr, u8 = self._frames, torch.uint8
+        dev = -1 if self.device.type == "cpu" else self.device.index
         for i, f in enumerate(frames):
             if f is None:
+                arr[i] = None
                 continue
-            w, h = self.geoms[i]
-            if (not isinstance(f, torch.Tensor) or f.dtype != torch.uint8 or f.device != self.device
-                    or not f.is_contiguous() or tuple(f.shape) != (h, w, 3)):
+            if (not isinstance(f, torch.Tensor) or f.dtype is not u8 or f.shape != self._shapes[i]
+                    or f.get_device() != dev or not f.is_contiguous()):
+                h, w, _ = self._shapes[i]
                 raise FiziError(FIZI_EINVAL, f"frame {i} must be a contiguous uint8 ({h}, {w}, 3) "
                                              f"tensor on {self.device}")
+            arr[i] = f.data_ptr()
         if (not isinstance(pointers, torch.Tensor) or pointers.dtype != torch.uint8
                 or pointers.device != self.device or not pointers.is_contiguous()
                 or tuple(pointers.shape) != (self.n, 56)):
@@ -409,20 +417,13 @@ class Batch:
                         or not f.is_contiguous() or tuple(f.shape) != (h, w // 64)):
                     raise FiziError(FIZI_EINVAL, f"mask {i} must be a contiguous int64 ({h}, {w // 64}) "
                                                  f"tensor on {self.device}")
-
-    def _frame_array(self, frames):
-        """Every entry of the reusable ctypes array is set (NULL when idle)."""
-        for i in range(self.n):
-            f = frames[i]
-            self._frames[i] = f.data_ptr() if f is not None else None
-        return self._frames
+        return arr
 
     def step(self, frames, pointers: torch.Tensor, fizi=None, stream=None):
         """frames: list of n device frames (H, W, 3) uint8 or None (idle);
         pointers: (n, 56) uint8 device tensor; fizi: optional list of n bit
         tensors (H, W/64) int64 (entries may be None)."""
-        self._check_step(frames, pointers, fizi)
-        fr = self._frame_array(frames)
+        fr = self._check_step(frames, pointers, fizi)
         fz = None
         if fizi is not None:
             for i in range(self.n):
@@ -450,8 +451,7 @@ class Batch:
     def autotune(self, frames, pointers, steps=5, stream=None):
         """Times candidate launch shapes on these frames; keeps the fastest.
         Returns (tuning dict, ms per step)."""
-        self._check_step(frames, pointers, None)
-        fr = self._frame_array(frames)
+        fr = self._check_step(frames, pointers, None)
         t, ms = Tuning(), ctypes.c_double()
         check(lib().fizi_batch_autotune(self._h, fr, _ptr(pointers), int(steps), _stream(stream),
                                         ctypes.byref(t), ctypes.byref(ms)))

@@ -19,6 +19,7 @@ def _batch(geoms):
     import ctypes
     b._frames = (ctypes.c_void_p * b.n)()
     b._fizi = (ctypes.c_void_p * b.n)()
+    b._shapes = [(h, w, 3) for w, h in b.geoms]
     return b
 
 
@@ -74,8 +75,8 @@ def test_every_entry_is_rewritten():
     """An idle stream's entry is NULL even when the previous step gave it a
     frame (no stale address survives from one step to the next)."""
     b = _batch(GEOMS)
-    frames, _, _ = _good()
-    arr = b._frame_array(frames)
+    frames, ptrs, _ = _good()
+    arr = b._check_step(frames, ptrs, None)
     assert arr[0] and arr[1]
-    arr = b._frame_array([None, frames[1]])
+    arr = b._check_step([None, frames[1]], ptrs, None)
     assert arr[0] is None and arr[1] == frames[1].data_ptr()
