@@ -213,20 +213,36 @@ int process_frames(fizi_ctx *ctx, const uint8_t *d_frames, int32_t n_frames,
 
 /* Temporal tracking of the hand (the Mouse module "tracks" the hand zone,
  * Section 2): with enable != 0, when the previous frame had a hand, the
- * component that covers its centroid pixel (floor of the coordinate sums over
- * the area) keeps the hand if its area reaches min_area; otherwise the
- * largest component is taken, as without tracking. Frames of a call are
- * tracked in order (their component stage then runs one frame after the
- * other). Waits for the context's work and clears the tracking state. */
+ * component nearest its centroid pixel (floor of the coordinate sums over the
+ * area; the one covering it first) within track_radius keeps the hand if its
+ * area reaches min_area (see fizi_params::track_radius); otherwise the
+ * largest component is taken, as without tracking. Frames are tracked in
+ * order across calls. Waits for the context's work (a pending pipelined
+ * call included) and clears the tracking state. */
 int fizi_set_tracking(fizi_ctx *ctx, int32_t enable);
+
+/* Pipelined calls, for a stream processed in back-to-back calls: with
+ * enable != 0, a call leaves the morphology and components of its last
+ * internal batch running on the context's side stream instead of waiting for
+ * them before its end, and the next call joins them after its first batch's
+ * classify, so that they run beside it. A call's outputs (masks, pointers)
+ * are then complete on its stream once the next call, or fizi_flush, has
+ * completed there; its input frames may be reused as soon as the call has
+ * completed. get_pointer waits on its own. Waits for the context's work;
+ * enable == 0 restores calls that complete their outputs themselves. */
+int fizi_set_pipelined(fizi_ctx *ctx, int32_t enable);
+
+/* Completes every call's outputs on `stream` (orders it after a pending
+ * pipelined call's last batch). Async. */
+int fizi_flush(fizi_ctx *ctx, void *stream);
 
 /* Waits for the frame with running index frame_index and copies its pointer
  * to *h_out. The last 65536 frames are kept; older or not yet submitted
  * indices give FIZI_ERANGE. */
 int get_pointer(fizi_ctx *ctx, int64_t frame_index, fizi_pointer *h_out);
 
-/* Waits for the context's work, releases its host resources. Frees nothing
- * the caller owns. */
+/* Waits for the context's work (a pending pipelined call included),
+ * releases its host resources. Frees nothing the caller owns. */
 int fizi_destroy(fizi_ctx *ctx);
 
 /* Measurement hook. With enable != 0 the context records a HIP event pair

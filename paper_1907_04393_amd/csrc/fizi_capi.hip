@@ -71,6 +71,13 @@ struct fizi_ctx {
     // front, the job tables going up on their own stream
     hipStream_t side = nullptr, up = nullptr;
     hipEvent_t up_ev[2] = {}, cls_ev[2] = {}, join_ev[2] = {};
+    // pipelined calls (fizi_set_pipelined): a call leaves its last chunk's
+    // back half on the side stream; the next call joins it after its first
+    // classify (or fizi_flush does), and chunks keep alternating raw buffers
+    // across calls
+    bool pipe_calls = false;
+    int parity = 0;      // raw buffer of the next chunk
+    int pend_join = -1;  // parity of the back half not yet joined, or -1
 };
 
 namespace {
@@ -88,6 +95,29 @@ int mark_last(fizi_ctx *c, hipStream_t s)
     FIZI_HIP(hipEventRecord(c->order_ev, s));
     c->last_stream = s;
     c->have_last = true;
+    return FIZI_OK;
+}
+
+// Orders s after the back half a pipelined call left pending.
+int join_pending(fizi_ctx *c, hipStream_t s)
+{
+    if (c->pend_join >= 0) {
+        FIZI_HIP(hipStreamWaitEvent(s, c->join_ev[c->pend_join], 0));
+        c->pend_join = -1;
+    }
+    return FIZI_OK;
+}
+
+// Joins a pending back half on the stream of the last call and waits for
+// all of the context's work.
+int drain(fizi_ctx *c)
+{
+    if (c->pend_join >= 0) {
+        FIZI_TRY(join_pending(c, c->last_stream));
+        FIZI_TRY(mark_last(c, c->last_stream));
+    }
+    if (c->have_last)
+        FIZI_HIP(hipEventSynchronize(c->order_ev));
     return FIZI_OK;
 }
 
@@ -230,6 +260,7 @@ int learn_background(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, int
         return fail(FIZI_ESTATE, "learning without reset needs a learned model");
     hipStream_t s = static_cast<hipStream_t>(stream);
     FIZI_TRY(order_after_previous(c, s));
+    FIZI_TRY(join_pending(c, s));
     FIZI_TRY(learn_model(c->m, c->ring, c->tune, c->n_cu, d_frames, n_frames, reset, s, &c->clk));
     return mark_last(c, s);
 }
@@ -247,6 +278,8 @@ int relearn_background(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, c
         return fail(FIZI_ESTATE, "relearn_background before learn_background");
     hipStream_t s = static_cast<hipStream_t>(stream);
     FIZI_TRY(order_after_previous(c, s));
+    // the masks may come from a call whose back half is still pending
+    FIZI_TRY(join_pending(c, s));
     FIZI_TRY(learn_model(c->m, c->ring, c->tune, c->n_cu, d_frames, n_frames, 0, s, &c->clk, d_fizi_bits));
     return mark_last(c, s);
 }
@@ -267,9 +300,11 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
     const size_t W = c->m.g.width, H = c->m.g.height, px = W * H, words = H * (W / 64);
     fizi_pointer *internal = reinterpret_cast<fizi_pointer *>(c->d + c->L.ptrs);
     // several chunks: each chunk's back half runs beside the next chunk's
-    // front (on the side stream; s joins it before the call ends)
-    const bool pipelined = n_frames > c->chunk;
-    int par = 0, prev_join = -1, last_slot = -1;
+    // front (on the side stream; s joins it before the call ends, or, with
+    // pipelined calls, after the next call's first classify)
+    const bool pipelined = c->pipe_calls || n_frames > c->chunk;
+    int par = c->pipe_calls ? c->parity : 0;
+    int prev_join = c->pipe_calls ? c->pend_join : -1, last_slot = -1;
     for (int f0 = 0; f0 < n_frames; f0 += c->chunk) {
         const int k = std::min(c->chunk, n_frames - f0);
         int slot;
@@ -334,16 +369,26 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
         }
         (void)last;
     }
-    if (pipelined)
-        FIZI_HIP(hipStreamWaitEvent(s, c->join_ev[prev_join], 0));
+    // the stream the call's single pointer copy goes to: after every back
+    // half of the call
+    hipStream_t cs = s;
+    if (pipelined) {
+        if (c->pipe_calls) {
+            c->pend_join = prev_join;
+            c->parity = par;
+            cs = c->side;
+        } else {
+            FIZI_HIP(hipStreamWaitEvent(s, c->join_ev[prev_join], 0));
+        }
+    }
     if (d_pointers) {
-        FIZI_TRY(copy_to_ring(c, d_pointers, c->next_frame, n_frames, s));
-        FIZI_TRY(c->ring.finish(last_slot, s));
+        FIZI_TRY(copy_to_ring(c, d_pointers, c->next_frame, n_frames, cs));
+        FIZI_TRY(c->ring.finish(last_slot, cs));
         fizi_ctx::Rec &r = c->recs[c->next_rec];
         c->next_rec = (c->next_rec + 1) % kRecs;
         r.f0 = c->next_frame;
         r.f1 = c->next_frame + (uint64_t)n_frames;
-        FIZI_HIP(hipEventRecord(r.ev, s));
+        FIZI_HIP(hipEventRecord(r.ev, cs));
         r.valid = true;
     }
     c->next_frame += (uint64_t)n_frames;
@@ -391,12 +436,31 @@ int fizi_set_tracking(fizi_ctx *c, int32_t enable)
 {
     if (!c)
         return fail(FIZI_EINVAL, "null context");
-    if (c->have_last)
-        FIZI_HIP(hipEventSynchronize(c->order_ev));
+    FIZI_TRY(drain(c));
     FIZI_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(c->m.track), 0u, sizeof(TrackState) / 4, nullptr));
     FIZI_HIP(hipStreamSynchronize(nullptr));
     c->m.tracking = enable != 0;
     return FIZI_OK;
+}
+
+int fizi_set_pipelined(fizi_ctx *c, int32_t enable)
+{
+    if (!c)
+        return fail(FIZI_EINVAL, "null context");
+    FIZI_TRY(drain(c));
+    c->pipe_calls = enable != 0;
+    c->parity = 0;
+    return FIZI_OK;
+}
+
+int fizi_flush(fizi_ctx *c, void *stream)
+{
+    if (!c)
+        return fail(FIZI_EINVAL, "null context");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FIZI_TRY(order_after_previous(c, s));
+    FIZI_TRY(join_pending(c, s));
+    return mark_last(c, s);
 }
 
 int fizi_destroy(fizi_ctx *c)
@@ -405,6 +469,9 @@ int fizi_destroy(fizi_ctx *c)
         return FIZI_OK;
     if (c->have_last)
         (void)hipEventSynchronize(c->order_ev);
+    // a pending back half, without touching the stream of the last call
+    if (c->pend_join >= 0)
+        (void)hipEventSynchronize(c->join_ev[c->pend_join]);
     c->ring.destroy();
     c->clk.destroy();
     if (c->h_ring)

@@ -102,6 +102,8 @@ def lib():
     L.learn_background.argtypes = [vp, vp, i32, i32, vp]
     L.relearn_background.argtypes = [vp, vp, i32, vp, vp]
     L.fizi_set_tracking.argtypes = [vp, i32]
+    L.fizi_set_pipelined.argtypes = [vp, i32]
+    L.fizi_flush.argtypes = [vp, vp]
     L.process_frames.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     L.get_pointer.argtypes = [vp, i64, P(PointerC)]
     L.fizi_destroy.argtypes = [vp]
@@ -217,6 +219,9 @@ class Context:
             raise FiziError(FIZI_EINVAL, "chunk must be in [1, 256]")
         self.device = _device(device)
         self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._pipelined = False
+        # outputs a pipelined call is still writing (see set_pipelined)
+        self._held = None
         self._h = ctypes.c_void_p()
         check(L.fizi_create(ctypes.byref(self.geom), ctypes.byref(self.params), self.chunk,
                             _ptr(self.state), nbytes, _stream(stream), ctypes.byref(self._h)))
@@ -245,6 +250,20 @@ class Context:
         """Temporal tracking of the hand zone (see fizi_set_tracking)."""
         check(lib().fizi_set_tracking(self._h, int(bool(enable))))
 
+    def set_pipelined(self, enable=True):
+        """Pipelined calls (see fizi_set_pipelined): a call's outputs are
+        complete once the next call, or flush(), has completed on its stream.
+        Until then the context keeps a reference to them, so that their
+        memory is not handed out while they are still being written."""
+        check(lib().fizi_set_pipelined(self._h, int(bool(enable))))
+        self._pipelined = bool(enable)
+        self._held = None
+
+    def flush(self, stream=None):
+        """Completes every call's outputs on the stream."""
+        check(lib().fizi_flush(self._h, _stream(stream)))
+        self._held = None
+
     def _check_bits(self, bits, n):
         if (bits.dtype != torch.int64 or not bits.is_contiguous()
                 or tuple(bits.shape) != (n, self.height, self.width // 64)):
@@ -264,12 +283,16 @@ class Context:
             ptrs = torch.empty((n, 56), dtype=torch.uint8, device=self.device)
         check(lib().process_frames(self._h, _ptr(frames), n, _ptr(fz), _ptr(hd), _ptr(ptrs),
                                    _stream(stream)))
+        if self._pipelined:
+            self._held = (fz, hd, ptrs)
         return dict(pointers=ptrs, fizi=fz, hand=hd)
 
     def process_into(self, frames, n, fizi=None, hand=None, pointers=None, stream=None):
         """process_frames into caller tensors (no allocation)."""
         check(lib().process_frames(self._h, _ptr(frames), int(n), _ptr(fizi), _ptr(hand),
                                    _ptr(pointers), _stream(stream)))
+        if self._pipelined:
+            self._held = (fizi, hand, pointers)
 
     def get_pointer(self, frame_index: int) -> dict:
         out = PointerC()
