@@ -3,8 +3,9 @@ morphology and components of its last internal batch running on the
 context's side stream, and the next call, or a flush, completes them. On the
 same frames every I_FIZI bit, hand bit and pointer equals the oracle's:
 through calls of several batches and of one, a switch of stream between
-calls, tracking across calls, get_pointer before any flush, and one output
-buffer reused by every call."""
+calls, tracking across calls, get_pointer before any flush, one output
+buffer reused by every call, and partial re-learning from a call that is
+still pending."""
 import numpy as np
 import pytest
 import torch
@@ -123,3 +124,29 @@ def test_switching_pipelining_off_completes_pending_work():
         for k in range(n):
             assert ptrs[k] == ref[lo + k]["pointer"], lo + k
             assert np.array_equal(fz[k], ref[lo + k]["fizi"]), lo + k
+
+
+def test_relearn_from_a_pending_call():
+    """Partial re-learning fed with the masks of a pipelined call that has
+    not been flushed: the context orders it after that call's last batch, so
+    the model, and the next call's outputs, equal those of a context whose
+    calls complete their own outputs."""
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    bg, hand = _scene()
+    hd = hand.to(dev)
+    res = []
+    for pipelined in (False, True):
+        ctx = fizi.Context(W, H, chunk=8, device=dev)
+        ctx.learn_background(bg.to(dev))
+        ctx.set_pipelined(pipelined)
+        a = ctx.process_frames(hd[:20].contiguous(), want_fizi=True)
+        ctx.relearn_background(hd[:20].contiguous(), a["fizi"])
+        b = ctx.process_frames(hd[20:40].contiguous(), want_fizi=True)
+        ctx.flush()
+        torch.cuda.synchronize()
+        bgmin, bgmax, _ = ctx.model()
+        res.append((bgmin.cpu().numpy(), bgmax.cpu().numpy(), b["pointers"].cpu().numpy(),
+                    b["fizi"].cpu().numpy()))
+    for x, y in zip(res[0], res[1]):
+        assert np.array_equal(x, y)
