@@ -3,6 +3,7 @@
 // pixel's BT.601 chroma (Cb, Cr) from (mu_b, mu_r) under the covariance
 // [[s_bb, s_br], [s_br, s_rr]]. Per-pixel arithmetic in FP32; gradient and
 // loss sums in FP64, reduced in a fixed order (bitwise reproducible).
+#include <atomic>
 #include <cmath>
 #include <mutex>
 
@@ -17,41 +18,47 @@ constexpr int kSoftBlocksMax = 2048;
 constexpr int kSoftOut = 8;        // 6 gradients, loss, unused
 constexpr int kSoftU = 4;          // pixel groups per thread and iteration of the adjoint
 
+// The inverse covariance P = S^-1 factors as P = L L^T, L lower triangular
+// (S is positive definite), so that q = delta^T P delta = |w|^2 with w = L^T
+// delta. Each component of w is an affine function of the pixel's R, G, B
+// (the chroma transform folded in on the host), so a pixel costs two affine
+// forms and one sum of squares. The gradient sums are taken in the w basis
+// and brought back to u = P delta = L w once per workgroup, in FP64.
 struct SoftParams {
-    float kb, kr;                  // 128 - mu_b, 128 - mu_r: chroma offset less the mean
-    float p_bb, p_br, p_rr;        // inverse covariance
+    float w1[4], w2[4];            // w_i = c0 + cR R + cG G + cB B, coefficients (c0, cR, cG, cB)
     float z0, z1;                  // z log2(e) = z0 - z1 d: theta / T and 1 / T, times log2(e)
+};
+
+struct SoftChol {
+    double l11, l21, l22;          // L = [[l11, 0], [l21, l22]]
 };
 
 // z is kept in base-2 units (z log2 e), so that the exponential and the
 // logarithm are single hardware instructions with no scaling; rs = 1 / d;
-// e = exp(-|z|).
+// e = exp(-|z|); rc = 1 / (1 + e).
 struct SoftPx {
-    float m, z, rs, e, ub, ur;
+    float m, z, rs, e, rc, w1, w2;
 };
 
 // Three transcendentals per pixel, each one hardware instruction (about one
 // ulp, far inside the relative 1e-4 the calibration form needs): one
 // reciprocal square root gives d and 1 / d, one exponential gives the
-// sigmoid (and the BCE's softplus), one reciprocal. q is a positive
-// definite form, 0 only where the pixel's chroma is the mean (u = 0, so
-// every gradient term is 0 whatever rs); it is held at 2^-100 there, so
-// that rs = 2^50 and d = 2^-50 stay finite (the reading d = 0, up to a z
-// change far below FP32 resolution). A q that small otherwise needs a
-// covariance eigenvalue below 1e-20.
+// sigmoid (and the BCE's softplus), one reciprocal. q = |w|^2 is 0 only
+// where the pixel's chroma is the mean (w = 0, so every gradient term is 0
+// whatever rs); 2^-100 is added to it, which changes no q above 2^-74 after
+// rounding and holds rs = 2^50 and d = 2^-50 finite at the mean (the
+// reading d = 0, up to a z change far below FP32 resolution).
 __device__ __forceinline__ SoftPx soft_px(float r, float g, float b, const SoftParams &s)
 {
-    const float db = fmaf(0.5f, b, fmaf(-0.331264f, g, fmaf(-0.168736f, r, s.kb)));
-    const float dr = fmaf(-0.081312f, b, fmaf(-0.418688f, g, fmaf(0.5f, r, s.kr)));
     SoftPx o;
-    o.ub = fmaf(s.p_bb, db, s.p_br * dr);
-    o.ur = fmaf(s.p_br, db, s.p_rr * dr);
-    const float q = fmaxf(fmaf(db, o.ub, dr * o.ur), 0x1p-100f);
+    o.w1 = fmaf(s.w1[3], b, fmaf(s.w1[2], g, fmaf(s.w1[1], r, s.w1[0])));
+    o.w2 = fmaf(s.w2[3], b, fmaf(s.w2[2], g, fmaf(s.w2[1], r, s.w2[0])));
+    const float q = fmaf(o.w1, o.w1, fmaf(o.w2, o.w2, 0x1p-100f));
     o.rs = __builtin_amdgcn_rsqf(q);
     o.z = fmaf(-s.z1, q * o.rs, s.z0);
     o.e = __builtin_amdgcn_exp2f(-fabsf(o.z));
-    const float rc = __builtin_amdgcn_rcpf(1.0f + o.e);
-    o.m = o.z >= 0.0f ? rc : o.e * rc;
+    o.rc = __builtin_amdgcn_rcpf(1.0f + o.e);
+    o.m = o.z >= 0.0f ? o.rc : o.e * o.rc;
     return o;
 }
 
@@ -85,23 +92,24 @@ __global__ __launch_bounds__(256) void k_soft_fwd(const uint8_t *__restrict__ fr
 // Adds one pixel's contributions (FP32) to acc, gz being dL/dz up to a
 // constant factor c. With u = S^-1 delta: dL/dmu = (gz / (T d)) u, dL/dS =
 // (gz / (2 T d)) u u^T (the off-diagonal entry counted twice) and dL/dtheta
-// = gz / T; the sums carry gz / d = gz rs and gz, and the constant factors
-// (c / T, c / T, c / 2T, c / T, c / 2T, c / T) are applied once, to the final
-// sums.
+// = gz / T. The sums carry gq = gz / d = gz rs times w and w w^T (u = L w),
+// and gz; the basis change and the constant factors (c / T, c / T, c / 2T,
+// c / T, c / 2T, c / T) are applied to the sums.
 __device__ __forceinline__ void soft_acc(const SoftPx &o, float gz, float *acc)
 {
     const float gq = gz * o.rs;
-    const float a = gq * o.ub, b = gq * o.ur;
+    const float a = gq * o.w1, b = gq * o.w2;
     acc[0] += a;
     acc[1] += b;
-    acc[2] = fmaf(a, o.ub, acc[2]);
-    acc[3] = fmaf(a, o.ur, acc[3]);
-    acc[4] = fmaf(b, o.ur, acc[4]);
+    acc[2] = fmaf(a, o.w1, acc[2]);
+    acc[3] = fmaf(a, o.w2, acc[3]);
+    acc[4] = fmaf(b, o.w2, acc[4]);
     acc[5] += gz;
 }
 
-// dL/dz of one pixel from the upstream dL/dm (c = 1).
-__device__ __forceinline__ float gz_upstream(const SoftPx &o, float dm) { return dm * fmaf(-o.m, o.m, o.m); }
+// dL/dz of one pixel from the upstream dL/dm (c = 1): dm m (1 - m), with
+// m (1 - m) = e / (1 + e)^2 for either sign of z.
+__device__ __forceinline__ float gz_upstream(const SoftPx &o, float dm) { return dm * (o.e * o.rc * o.rc); }
 
 // Fused BCE: dL/dz = (m - y) / N (c = 1 / N, applied to the sums), and the
 // pixel's BCE term in base-2 units, max(z, 0) - z y + log2(1 + e), is added
@@ -128,14 +136,30 @@ __device__ __forceinline__ void soft_group(uint32_t w0, uint32_t w1, uint32_t w2
     }
 }
 
+// Output k of a workgroup's sums t (taken in the w basis) in the u basis:
+// sum gq u = L sum gq w, sum gq u u^T = L (sum gq w w^T) L^T, the symmetric
+// sums stored as (bb, br, rr); gz and the loss pass through.
+__device__ __forceinline__ double to_u_basis(const double *t, int k, const SoftChol &L)
+{
+    switch (k) {
+    case 0: return L.l11 * t[0];
+    case 1: return fma(L.l21, t[0], L.l22 * t[1]);
+    case 2: return L.l11 * L.l11 * t[2];
+    case 3: return L.l11 * fma(L.l21, t[2], L.l22 * t[3]);
+    case 4: return fma(L.l21 * L.l21, t[2], fma(2.0 * L.l21 * L.l22, t[3], L.l22 * L.l22 * t[4]));
+    default: return t[k];
+    }
+}
+
 // VEC: dL/dm is 16-byte and the ground truth 4-byte aligned, so a group's
 // four values come in one load.
 template <bool BCE, bool VEC>
 __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ frames, const float *__restrict__ dLdm,
                                                   const uint8_t *__restrict__ gt, long long npx, SoftParams s,
-                                                  double *__restrict__ partial)
+                                                  SoftChol L, double *__restrict__ partial)
 {
     __shared__ double s_red[256 / 64][kSoftOut];
+    __shared__ double s_tot[kSoftOut];
     double acc[kSoftOut] = {0, 0, 0, 0, 0, 0, 0, 0};
     const long long groups = npx / 4;
     const uint32_t *f = reinterpret_cast<const uint32_t *>(frames);
@@ -209,8 +233,11 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const uint8_t *__restrict__ fr
         double v = 0.0;
         for (int w = 0; w < (int)(blockDim.x / 64); ++w)
             v += s_red[w][threadIdx.x];
-        partial[blockIdx.x * kSoftOut + threadIdx.x] = v;
+        s_tot[threadIdx.x] = v;
     }
+    __syncthreads();
+    if (threadIdx.x < kSoftOut)
+        partial[blockIdx.x * kSoftOut + threadIdx.x] = to_u_basis(s_tot, threadIdx.x, L);
 }
 
 struct SoftScale {
@@ -239,7 +266,11 @@ __global__ __launch_bounds__(256) void k_soft_final(const double *__restrict__ p
         out[k] = s[0] * scale.k[k];
 }
 
-int soft_params(const float p6[6], float T, SoftParams *s)
+// BT.601 chroma: Cb = 128 + cb . (R, G, B), Cr = 128 + cr . (R, G, B).
+constexpr double kCb[3] = {-0.168736, -0.331264, 0.5};
+constexpr double kCr[3] = {0.5, -0.418688, -0.081312};
+
+int soft_params(const float p6[6], float T, SoftParams *s, SoftChol *L)
 {
     if (!p6)
         return fail(FIZI_EINVAL, "null parameters");
@@ -249,24 +280,65 @@ int soft_params(const float p6[6], float T, SoftParams *s)
         return fail(FIZI_EINVAL, "covariance must be positive definite");
     if (!(T > 0.0f) || !std::isfinite(T))
         return fail(FIZI_EINVAL, "temperature must be positive");
+    // S^-1 = [[srr, -sbr], [-sbr, sbb]] / det = L L^T
+    SoftChol c;
+    c.l11 = std::sqrt(srr / det);
+    c.l21 = -sbr / std::sqrt(srr * det);
+    c.l22 = 1.0 / std::sqrt(srr);
+    // w = L^T delta: w1 = l11 db + l21 dr, w2 = l22 dr, with db = 128 - mu_b
+    // + cb . v and dr = 128 - mu_r + cr . v
+    const double kb = 128.0 - (double)p6[0], kr = 128.0 - (double)p6[1];
+    s->w1[0] = (float)(c.l11 * kb + c.l21 * kr);
+    s->w2[0] = (float)(c.l22 * kr);
+    for (int ch = 0; ch < 3; ++ch) {
+        s->w1[ch + 1] = (float)(c.l11 * kCb[ch] + c.l21 * kCr[ch]);
+        s->w2[ch + 1] = (float)(c.l22 * kCr[ch]);
+    }
     const double log2e = 1.4426950408889634, inv_t = 1.0 / (double)T;
-    s->kb = (float)(128.0 - (double)p6[0]);
-    s->kr = (float)(128.0 - (double)p6[1]);
-    s->p_bb = (float)(srr / det);
-    s->p_br = (float)(-sbr / det);
-    s->p_rr = (float)(sbb / det);
     s->z0 = (float)((double)p6[5] * inv_t * log2e);
     s->z1 = (float)(inv_t * log2e);
+    if (L)
+        *L = c;
     return FIZI_OK;
 }
 
-int soft_grid(long long npx)
+// Workgroups of a soft-mask launch: as many as are resident at once on the
+// device (the kernel's own occupancy: the adjoints hold 70-80 VGPRs, so 6 or
+// 7 of their workgroups fit a CU where the forward pass fits 8), at most one
+// per 256 pixel groups and kSoftBlocksMax. Every workgroup of the
+// grid-stride loops carries the same share of the pixels, so a grid larger
+// than what is resident would leave a second, partial round behind the
+// first. The occupancy is queried once per kernel.
+template <typename K>
+int soft_grid(K kernel, std::atomic<int> &per_cu, long long npx)
 {
     int dev = 0, n_cu = 0;
     if (device_cu_count(&dev, &n_cu) != FIZI_OK)
         n_cu = 256;
+    int nb = per_cu.load(std::memory_order_relaxed);
+    if (nb < 1) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb < 1)
+            nb = 8;
+        per_cu.store(nb, std::memory_order_relaxed);
+    }
     const long long groups = (npx / 4 + 255) / 256;
-    return (int)std::max<long long>(1, std::min<long long>(std::min(kSoftBlocksMax, n_cu * 8), groups));
+    return (int)std::max<long long>(1, std::min<long long>(std::min(kSoftBlocksMax, n_cu * nb), groups));
+}
+
+std::atomic<int> g_fwd_per_cu{0};
+std::atomic<int> g_bwd_per_cu[2][2];
+
+template <bool BCE, bool VEC>
+int bwd_grid(long long npx)
+{
+    return soft_grid(k_soft_bwd<BCE, VEC>, g_bwd_per_cu[BCE][VEC], npx);
+}
+
+int bwd_grid(bool bce, bool vec, long long npx)
+{
+    if (bce)
+        return vec ? bwd_grid<true, true>(npx) : bwd_grid<true, false>(npx);
+    return vec ? bwd_grid<false, true>(npx) : bwd_grid<false, false>(npx);
 }
 
 // Measurement hook of the soft-mask calls: dispatch events of each kernel
@@ -292,21 +364,23 @@ int soft_backward(const uint8_t *frames, const float *dLdm, const uint8_t *gt, l
     if (ws_bytes < (size_t)kSoftBlocksMax * kSoftOut * sizeof(double))
         return fail(FIZI_ENOMEM, "workspace smaller than fizi_soft_workspace_bytes()");
     SoftParams s;
-    FIZI_TRY(soft_params(p6, T, &s));
+    SoftChol L;
+    FIZI_TRY(soft_params(p6, T, &s, &L));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int grid = soft_grid(npx);
+    const bool vec = gt ? reinterpret_cast<uintptr_t>(gt) % 4 == 0 : reinterpret_cast<uintptr_t>(dLdm) % 16 == 0;
+    const int grid = bwd_grid(gt != nullptr, vec, npx);
     double *partial = static_cast<double *>(ws);
     const StageEvents ev = soft_ev(FIZI_SOFT_STAGE_BACKWARD);
     if (gt) {
-        if (reinterpret_cast<uintptr_t>(gt) % 4 == 0)
-            FIZI_LAUNCH((k_soft_bwd<true, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, partial);
+        if (vec)
+            FIZI_LAUNCH((k_soft_bwd<true, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, L, partial);
         else
-            FIZI_LAUNCH((k_soft_bwd<true, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, partial);
+            FIZI_LAUNCH((k_soft_bwd<true, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, L, partial);
     } else {
-        if (reinterpret_cast<uintptr_t>(dLdm) % 16 == 0)
-            FIZI_LAUNCH((k_soft_bwd<false, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, partial);
+        if (vec)
+            FIZI_LAUNCH((k_soft_bwd<false, true>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, L, partial);
         else
-            FIZI_LAUNCH((k_soft_bwd<false, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, partial);
+            FIZI_LAUNCH((k_soft_bwd<false, false>), grid, 256, 0, st, ev, frames, dLdm, gt, npx, s, L, partial);
     }
     FIZI_HIP(hipGetLastError());
     // dL/dmu_b, dL/dmu_r, dL/ds_bb, dL/ds_br, dL/ds_rr, dL/dtheta, loss: the
@@ -376,10 +450,10 @@ int fizi_soft_forward(const uint8_t *d_frames, int64_t npx, const float params6[
     if (reinterpret_cast<uintptr_t>(d_frames) % 4 != 0 || reinterpret_cast<uintptr_t>(d_mask) % 16 != 0)
         return fail(FIZI_EINVAL, "frames must be 4-byte and the mask 16-byte aligned");
     SoftParams s;
-    FIZI_TRY(soft_params(params6, T, &s));
+    FIZI_TRY(soft_params(params6, T, &s, nullptr));
     hipStream_t st = static_cast<hipStream_t>(stream);
     const StageEvents ev = soft_ev(FIZI_SOFT_STAGE_FORWARD);
-    FIZI_LAUNCH(k_soft_fwd, soft_grid(npx), 256, 0, st, ev, d_frames, npx, s, d_mask);
+    FIZI_LAUNCH(k_soft_fwd, soft_grid(k_soft_fwd, g_fwd_per_cu, npx), 256, 0, st, ev, d_frames, npx, s, d_mask);
     FIZI_HIP(hipGetLastError());
     return FIZI_OK;
 }
@@ -434,7 +508,8 @@ int fizi_soft_bce_static(const uint8_t *d_frames, const uint8_t *d_gt, int64_t n
 {
     if (!d_gt)
         return fail(FIZI_EINVAL, "null ground truth");
-    if (npx >= 1 && (size_t)soft_grid(npx) * kSoftOut * sizeof(double) > sizeof(scratch))
+    if (npx >= 1 && (size_t)bwd_grid(true, reinterpret_cast<uintptr_t>(d_gt) % 4 == 0, npx) * kSoftOut *
+                            sizeof(double) > sizeof(scratch))
         return fail(FIZI_ENOMEM, "the launch needs more partial sums than the 128 KiB static array holds");
     double *ws = nullptr;
     FIZI_TRY(scratch_of_current_device(&ws));
