@@ -311,9 +311,18 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
         FIZI_TRY(c->ring.take(&slot));
         Table &T = *c->ring.h[slot];
         const uint64_t fbase = c->next_frame + (uint64_t)f0;
+        // a launch whose morphology, in short bands of one wave each, needs
+        // at most one wave per SIMD is bound by the length of one wave's
+        // chain of rows rather than by the total work: it takes that shape
+        // (13 row steps per wave against 17 for 8-row bands). Larger launches
+        // keep the tuned shape, which repeats fewer halo rows.
+        const bool short_chain = (size_t)k * ((H + kShortBand - 1) / kShortBand) <= (size_t)c->n_cu * 4;
         for (int i = 0; i < k; ++i) {
             Job &J = T.jobs[i];
-            fill_job(c->m, c->tune.morph_rows, J);
+            if (short_chain)
+                fill_job(c->m, kShortBand, J, false);
+            else
+                fill_job(c->m, c->tune.morph_rows, J);
             set_scratch(J, slot_at(c->m.g, c->d + c->L.slots + (size_t)i * c->L.slot_stride));
             if (pipelined && par)
                 J.raw = reinterpret_cast<uint64_t *>(c->d + c->L.raw2 + (size_t)i * c->L.raw2_stride);

@@ -77,7 +77,12 @@ Slot slot_at(const fizi_geom &g, uint8_t *base);
 
 // Job for one frame of a stream: model and thresholds; the caller sets the
 // frame, scratch, outputs and frame index.
-void fill_job(const Model &m, int band, Job &J);
+// band: the morphology band height in rows; pack: narrow frames may share a
+// wave between bands (2 or 4 per wave)
+void fill_job(const Model &m, int band, Job &J, bool pack = true);
+
+// Morphology band height of launches too small to fill the device.
+constexpr int kShortBand = 4;
 void set_scratch(Job &J, const Slot &s);
 // Tile prefix arrays of a table whose first njobs jobs are filled.
 void set_prefixes(Table &T, int njobs, const Tuning &t);

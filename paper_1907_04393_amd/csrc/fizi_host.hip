@@ -187,7 +187,7 @@ Slot slot_at(const fizi_geom &g, uint8_t *base)
     return s;
 }
 
-void fill_job(const Model &m, int band, Job &J)
+void fill_job(const Model &m, int band, Job &J, bool pack)
 {
     std::memset(&J, 0, sizeof(J));
     J.bgmin = m.bgmin;
@@ -200,7 +200,7 @@ void fill_job(const Model &m, int band, Job &J)
     J.band = band;
     // narrow frames under the default opening and closing share a wave
     // between bands: 4 bands of at most 16 words, or 2 of at most 32
-    const bool packable = m.p.open_iters == 1 && m.p.close_iters == 1;
+    const bool packable = pack && m.p.open_iters == 1 && m.p.close_iters == 1;
     J.mgroup = !packable ? 64 : (J.Wd <= 16 ? 16 : (J.Wd <= 32 ? 32 : 64));
     J.delta = m.p.bg_delta;
     J.S1 = std::max(m.p.gray_S, 1);
@@ -244,7 +244,7 @@ void set_prefixes(Table &T, int njobs, const Tuning &t)
         const int rows = (J.H + J.rs - 1) / J.rs;
         T.h.gain_pre[i + 1] = T.h.gain_pre[i] + (rows + kGainRows - 1) / kGainRows;
         T.h.cls_pre[i + 1] = T.h.cls_pre[i] + (int)((px + ctile - 1) / ctile);
-        const int bands = (J.H + t.morph_rows - 1) / t.morph_rows, per = 64 / J.mgroup;
+        const int bands = (J.H + J.band - 1) / J.band, per = 64 / J.mgroup;
         T.h.mor_pre[i + 1] = T.h.mor_pre[i] + (bands + per - 1) / per;
     }
     // the persistent step's queue: jobs by size, largest first; every gain
@@ -259,7 +259,7 @@ void set_prefixes(Table &T, int njobs, const Tuning &t)
     int k = 0, item = 0;
     auto push = [&](int j, int type) {
         const int n = type == 0 ? T.h.gain_pre[j + 1] - T.h.gain_pre[j]
-                                : (T.jobs[j].H + 4 * t.morph_rows - 1) / (4 * t.morph_rows);
+                                : (T.jobs[j].H + 4 * T.jobs[j].band - 1) / (4 * T.jobs[j].band);
         T.h.flow_pre[k] = item;
         T.h.flow_seg[k] = (j << 1) | type;
         item += n;
