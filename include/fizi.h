@@ -236,6 +236,15 @@ int fizi_set_pipelined(fizi_ctx *ctx, int32_t enable);
  * pipelined call's last batch). Async. */
 int fizi_flush(fizi_ctx *ctx, void *stream);
 
+/* Launch shape of the context's morphology. With enable != 0 (the default)
+ * a launch too small to fill the device - its frames' morphology in 4-row
+ * bands of one wave each needs at most one wave per SIMD, as for one to
+ * three 1920x1080 frames - takes that shape: its length is then one wave's
+ * chain of rows rather than the work. With 0 every launch keeps 8-row bands
+ * (two or four to a wave for frames up to 2048 or 1024 pixels wide).
+ * Results do not depend on it; it applies from the next call. */
+int fizi_set_short_bands(fizi_ctx *ctx, int32_t enable);
+
 /* Waits for the frame with running index frame_index and copies its pointer
  * to *h_out. The last 65536 frames are kept; older or not yet submitted
  * indices give FIZI_ERANGE. */
@@ -341,13 +350,19 @@ int fizi_batch_stage_times(fizi_batch *b, double *h_ms, int64_t *h_launches);
  * pixels (1, 2, 4, 8; not used by the persistent kernel, whose classify
  * work comes in bands of 4 * morph_rows rows); morph_rows: morphology band
  * height (8, 16, 32, 64); grid_per_cu: resident blocks per CU for the
- * streaming kernels (1..64); mode: FIZI_BATCH_*. Results do not depend on
- * them. */
+ * streaming kernels (1..64); mode: FIZI_BATCH_*; short_bands (0, 1; 1 when
+ * the batch is created): a step too small to fill the device - its frames'
+ * morphology in 4-row bands of one wave each needs at most one wave per
+ * SIMD, as with the few active streams of a serving step - takes that
+ * shape instead of morph_rows in the four-kernel modes (its length is then
+ * one wave's chain of rows, not the work); 0 keeps morph_rows for every
+ * step. Results do not depend on them. */
 typedef struct {
     int32_t cls_iters;
     int32_t morph_rows;
     int32_t grid_per_cu;
     int32_t mode;
+    int32_t short_bands;
 } fizi_tuning;
 
 int fizi_batch_get_tuning(fizi_batch *b, fizi_tuning *out);

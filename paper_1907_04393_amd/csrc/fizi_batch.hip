@@ -444,12 +444,24 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
     FIZI_TRY(b->ring.take(&slot));
     Table &T = *b->ring.h[slot];
     const bool pipelined = is_pipelined(b->mode);
+    // a step too small to fill the device (a few active streams, as in
+    // serving) takes the contexts' short morphology bands when the four
+    // kernels run it; the persistent step keeps the tuned bands
+    size_t short_waves = 0;
+    for (int i = 0; i < b->n; ++i)
+        if (h_frames[i])
+            short_waves += (size_t)((b->m[i].g.height + kShortBand - 1) / kShortBand);
+    const bool short_chain = b->tune.short_bands && b->mode != FIZI_BATCH_PERSISTENT &&
+                             b->mode != FIZI_BATCH_PERSISTENT_GRAPH && short_waves <= (size_t)b->n_cu * 4;
     int k = 0;
     for (int i = 0; i < b->n; ++i) {
         if (!h_frames[i])
             continue;
         Job &J = T.jobs[k++];
-        fill_job(b->m[i], b->tune.morph_rows, J);
+        if (short_chain)
+            fill_job(b->m[i], kShortBand, J, false);
+        else
+            fill_job(b->m[i], b->tune.morph_rows, J);
         set_scratch(J, b->slot[i]);
         if (pipelined && b->parity)
             J.raw = b->raw2[i];
@@ -518,6 +530,7 @@ int fizi_batch_get_tuning(fizi_batch *b, fizi_tuning *out)
     out->morph_rows = b->tune.morph_rows;
     out->grid_per_cu = b->tune.grid_per_cu;
     out->mode = b->mode;
+    out->short_bands = b->tune.short_bands;
     return FIZI_OK;
 }
 
@@ -531,6 +544,8 @@ int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t)
         return fail(FIZI_EINVAL, "morph_rows must be 8, 16, 32 or 64");
     if (t->grid_per_cu < 1 || t->grid_per_cu > 64)
         return fail(FIZI_EINVAL, "grid_per_cu must be in [1, 64]");
+    if (t->short_bands != 0 && t->short_bands != 1)
+        return fail(FIZI_EINVAL, "short_bands must be 0 or 1");
     if (t->mode < FIZI_BATCH_DIRECT || t->mode > FIZI_BATCH_PIPELINED_GRAPH)
         return fail(FIZI_EINVAL, "unknown batch mode");
     FIZI_TRY(drain(b));
@@ -538,6 +553,7 @@ int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t)
     b->tune.cls_iters = t->cls_iters;
     b->tune.morph_rows = t->morph_rows;
     b->tune.grid_per_cu = t->grid_per_cu;
+    b->tune.short_bands = t->short_bands;
     b->mode = t->mode;
     return FIZI_OK;
 }

@@ -316,7 +316,8 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
         // chain of rows rather than by the total work: it takes that shape
         // (13 row steps per wave against 17 for 8-row bands). Larger launches
         // keep the tuned shape, which repeats fewer halo rows.
-        const bool short_chain = (size_t)k * ((H + kShortBand - 1) / kShortBand) <= (size_t)c->n_cu * 4;
+        const bool short_chain =
+            c->tune.short_bands && (size_t)k * ((H + kShortBand - 1) / kShortBand) <= (size_t)c->n_cu * 4;
         for (int i = 0; i < k; ++i) {
             Job &J = T.jobs[i];
             if (short_chain)
@@ -459,6 +460,14 @@ int fizi_set_pipelined(fizi_ctx *c, int32_t enable)
     FIZI_TRY(drain(c));
     c->pipe_calls = enable != 0;
     c->parity = 0;
+    return FIZI_OK;
+}
+
+int fizi_set_short_bands(fizi_ctx *c, int32_t enable)
+{
+    if (!c)
+        return fail(FIZI_EINVAL, "null context");
+    c->tune.short_bands = enable != 0;
     return FIZI_OK;
 }
 

@@ -124,6 +124,7 @@ struct Tuning {
     int cls_iters;      // classify tile = 1024 * cls_iters pixels (1, 2, 4, 8)
     int morph_rows;     // morphology band height (8, 16, 32, 64)
     int grid_per_cu;    // resident blocks per CU for the streaming kernels
+    int short_bands = 1;   // launches too small to fill the device take short morphology bands
 };
 
 inline int cls_tile_px(const Tuning &t) { return 1024 * t.cls_iters; }

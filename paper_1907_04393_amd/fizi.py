@@ -45,7 +45,7 @@ class PointerC(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("cls_iters", ctypes.c_int32), ("morph_rows", ctypes.c_int32),
-                ("grid_per_cu", ctypes.c_int32), ("mode", ctypes.c_int32)]
+                ("grid_per_cu", ctypes.c_int32), ("mode", ctypes.c_int32), ("short_bands", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -103,6 +103,7 @@ def lib():
     L.relearn_background.argtypes = [vp, vp, i32, vp, vp]
     L.fizi_set_tracking.argtypes = [vp, i32]
     L.fizi_set_pipelined.argtypes = [vp, i32]
+    L.fizi_set_short_bands.argtypes = [vp, i32]
     L.fizi_flush.argtypes = [vp, vp]
     L.process_frames.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     L.get_pointer.argtypes = [vp, i64, P(PointerC)]
@@ -258,6 +259,11 @@ class Context:
         check(lib().fizi_set_pipelined(self._h, int(bool(enable))))
         self._pipelined = bool(enable)
         self._held = None
+
+    def set_short_bands(self, enable=True):
+        """Short morphology bands for launches too small to fill the device
+        (see fizi_set_short_bands); results do not depend on it."""
+        check(lib().fizi_set_short_bands(self._h, int(bool(enable))))
 
     def flush(self, stream=None):
         """Completes every call's outputs on the stream."""

@@ -11,13 +11,14 @@ def need_gpu():
     return torch.device("cuda:0")
 
 
-def gpu_run(bg, hand, params: dict, chunk=16, learn_split=None, want_hand=True):
+def gpu_run(bg, hand, params: dict, chunk=16, learn_split=None, want_hand=True, short_bands=True):
     """bg, hand: (n, H, W, 3) uint8 CPU tensors. Returns a dict of numpy
     outputs of the HIP path."""
     from paper_1907_04393_amd import fizi
     dev = need_gpu()
     H, W = bg.shape[1], bg.shape[2]
     ctx = fizi.Context(W, H, fizi.default_params(**params), chunk=chunk, device=dev)
+    ctx.set_short_bands(short_bands)
     bgd = bg.to(dev).contiguous()
     if learn_split:
         s = 0

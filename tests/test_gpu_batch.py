@@ -202,9 +202,13 @@ def test_every_launch_shape_gives_the_same_result():
     hands = [h.to(dev) for _, h in data]
     b.set_tuning(mode=0, cls_iters=4, morph_rows=32, grid_per_cu=8)
     ref = _run_steps(b, hands, specs, 2, dev)
-    shapes = [dict(mode=m, cls_iters=c, morph_rows=r, grid_per_cu=g)
+    # these streams are small enough for the short morphology bands, so
+    # every tuned band height is taken with them off, and the short bands
+    # once per four-kernel mode
+    shapes = [dict(mode=m, cls_iters=c, morph_rows=r, grid_per_cu=g, short_bands=0)
               for m in MODES for c in (2, 8) for r in (8, 64) for g in ((1, 16) if m in (0, 4) else (8,))]
-    shapes += [dict(mode=0, cls_iters=1, morph_rows=16, grid_per_cu=4)]
+    shapes += [dict(mode=0, cls_iters=1, morph_rows=16, grid_per_cu=4, short_bands=0)]
+    shapes += [dict(mode=m, cls_iters=4, morph_rows=16, grid_per_cu=8, short_bands=1) for m in (0, 1, 4, 5)]
     for sh in shapes:
         print("shape", sh, flush=True)
         b.set_tuning(**sh)
@@ -233,7 +237,8 @@ def test_autotune_keeps_results():
 
 def test_dense_masks_every_band_height():
     """Dense run masks (segment seams, rows of over 512 runs) at every band
-    height and in the direct and persistent launch modes."""
+    height and in the direct, persistent and pipelined launch modes, and in
+    the short bands of one wave each."""
     from test_gpu_plain import dense_frames
     from paper_1907_04393_amd import fizi
     dev = need_gpu()
@@ -250,43 +255,46 @@ def test_dense_masks_every_band_height():
     for i, (bg, _) in enumerate(data):
         b.learn(i, bg.to(dev))
     hands = [h.to(dev) for _, h in data]
-    for mode in (0, 2, 4):
-        for rows in (8, 16, 32, 64):
-            print("dense batch mode", mode, "rows", rows, flush=True)
-            b.set_tuning(mode=mode, cls_iters=4, morph_rows=rows, grid_per_cu=8)
-            bufs = []
-            for k in range(2):
-                ptrs = torch.empty((len(cases), 56), dtype=torch.uint8, device=dev)
-                fz = [torch.empty((H, W // 64), dtype=torch.int64, device=dev) for W, H, _ in cases]
-                b.step([h[k] for h in hands], ptrs, fizi=fz)
-                bufs.append((ptrs, fz))
-            b.flush()
-            torch.cuda.synchronize()
-            for k, (ptrs, fz) in enumerate(bufs):
-                got = fizi.pointers_to_numpy(ptrs)
-                for i, (W, H, kind) in enumerate(cases):
-                    p = fizi.pointer_dict(got[i])
-                    ref = dict(orc[i][k]["pointer"])
-                    p.pop("frame_index"), ref.pop("frame_index")
-                    assert p == ref, (mode, rows, k, kind)
-                    assert np.array_equal(fizi.unpack_bits(fz[i], W), orc[i][k]["fizi"]), (mode, rows, k, kind)
-            assert b.status() == 0
+    # every tuned band height (short bands off), then the short bands
+    shapes = [(mode, rows, 0) for mode in (0, 2, 4) for rows in (8, 16, 32, 64)] + [(0, 16, 1), (4, 16, 1)]
+    for mode, rows, short in shapes:
+        print("dense batch mode", mode, "rows", rows, "short bands", short, flush=True)
+        b.set_tuning(mode=mode, cls_iters=4, morph_rows=rows, grid_per_cu=8, short_bands=short)
+        bufs = []
+        for k in range(2):
+            ptrs = torch.empty((len(cases), 56), dtype=torch.uint8, device=dev)
+            fz = [torch.empty((H, W // 64), dtype=torch.int64, device=dev) for W, H, _ in cases]
+            b.step([h[k] for h in hands], ptrs, fizi=fz)
+            bufs.append((ptrs, fz))
+        b.flush()
+        torch.cuda.synchronize()
+        for k, (ptrs, fz) in enumerate(bufs):
+            got = fizi.pointers_to_numpy(ptrs)
+            for i, (W, H, kind) in enumerate(cases):
+                p = fizi.pointer_dict(got[i])
+                ref = dict(orc[i][k]["pointer"])
+                p.pop("frame_index"), ref.pop("frame_index")
+                assert p == ref, (mode, rows, k, kind)
+                assert np.array_equal(fizi.unpack_bits(fz[i], W), orc[i][k]["fizi"]), (mode, rows, k, kind)
+        assert b.status() == 0
     b.close()
 
 
-@pytest.mark.parametrize("mode", MODES)
-def test_batch_wide_and_narrow_streams(mode):
+@pytest.mark.parametrize("mode,short", [(m, 0) for m in MODES] + [(0, 1), (4, 1)])
+def test_batch_wide_and_narrow_streams(mode, short):
     """An 8192-pixel-wide stream beside narrow ones: the morphology launch
     takes two words per lane, and the narrow frames' packed bands run inside
-    it with one."""
+    it with one (short bands off); with short bands on, every frame takes
+    4-row bands of one wave each."""
     from oracle import oracle
     from test_gpu_plain import _blob_scene
     from paper_1907_04393_amd import fizi
     dev = need_gpu()
     shapes = [(8192, 24), (640, 48), (1920, 33), (1280, 17)]
-    print("wide and narrow, mode", mode, flush=True)
+    print("wide and narrow, mode", mode, "short bands", short, flush=True)
     b = fizi.Batch(shapes, device=dev)
     b.set_mode(mode)
+    b.set_tuning(short_bands=short)
     data, orc = [], []
     for i, (W, H) in enumerate(shapes):
         bg, hand = _blob_scene(W, H, 3, 3, seed=31 * i + W)

@@ -16,12 +16,14 @@ def _small():
     return sc.bg_frames(0, 30), sc.hand_frames(0, 100)
 
 
-def test_small_scene_full_parity():
+@pytest.mark.parametrize("short_bands", [True, False])
+def test_small_scene_full_parity(short_bands):
     """320x240, 30 background + 100 hand frames, chunks of 16 (ragged last
-    chunk)."""
+    chunk); launches this small take 4-row morphology bands of one wave
+    each unless short bands are off (8-row bands, two to a wave)."""
     bg, hand = _small()
-    print("small scene: 320x240, 30 bg + 100 hand", flush=True)
-    g = gpu_run(bg, hand, {}, chunk=16)
+    print("small scene: 320x240, 30 bg + 100 hand, short bands", short_bands, flush=True)
+    g = gpu_run(bg, hand, {}, chunk=16, short_bands=short_bands)
     m, outs = oracle_run(bg, hand, {})
     compare(g, m, outs, "small")
     assert sum(o["pointer"]["present"] for o in outs.values()) >= 95
@@ -211,15 +213,17 @@ def test_hue_gray_all_2e24_colours():
         del out
 
 
-def test_hd_scene_parity():
+@pytest.mark.parametrize("chunk", [16, 1])
+def test_hd_scene_parity(chunk):
     """1920x1080, sigma 5, two distractors, 50 background frames, 32 hand
-    frames in chunks of 16."""
+    frames in chunks of 16 (8-row morphology bands, two to a wave) or one
+    by one (4-row bands of one wave each, the latency shape)."""
     from paper_1907_04393_amd import scene
     sc = scene.Scene(scene.hd_plain())
     bg = sc.bg_frames(0, 50)
     hand = sc.hand_frames(0, 32)
-    print("hd scene 1920x1080", flush=True)
-    g = gpu_run(bg, hand, {}, chunk=16)
+    print("hd scene 1920x1080, chunk", chunk, flush=True)
+    g = gpu_run(bg, hand, {}, chunk=chunk)
     m, outs = oracle_run(bg, hand, {})
     compare(g, m, outs, "hd")
     assert all(o["pointer"]["present"] for o in outs.values())
