@@ -53,9 +53,14 @@ struct fizi_ctx {
     int n_cu = 0;
     TableRing ring;
     StageClock clk;
+    // the last kRing pointers, indexed by frame: pinned, coherent host memory
+    // that the component kernels store each final pointer into (d_ring is
+    // its device-side address), so that no copy follows them
     fizi_pointer *h_ring = nullptr;
+    fizi_pointer *d_ring = nullptr;
     // frames [f0, f1) are in the host pointer ring once `ev` (recorded after
-    // their copy, default fences: the host reads what the copy wrote) is done
+    // the kernels that store them, default fences: the host reads what they
+    // wrote) is done
     struct Rec {
         uint64_t f0, f1;
         hipEvent_t ev;
@@ -118,26 +123,6 @@ int drain(fizi_ctx *c)
     }
     if (c->have_last)
         FIZI_HIP(hipEventSynchronize(c->order_ev));
-    return FIZI_OK;
-}
-
-// Copies n pointers of consecutive frames starting at running index f into
-// the host ring (split where the ring wraps; only the newest kRing kept).
-int copy_to_ring(fizi_ctx *c, const fizi_pointer *src, uint64_t f, int n, hipStream_t s)
-{
-    if (n > kRing) {
-        src += n - kRing;
-        f += (uint64_t)(n - kRing);
-        n = kRing;
-    }
-    int done = 0;
-    while (done < n) {
-        const size_t pos = (size_t)((f + done) % kRing);
-        const int k = (int)std::min<size_t>(n - done, kRing - pos);
-        FIZI_HIP(hipMemcpyAsync(c->h_ring + pos, src + done, k * sizeof(fizi_pointer),
-                                hipMemcpyDeviceToHost, s));
-        done += k;
-    }
     return FIZI_OK;
 }
 
@@ -220,7 +205,9 @@ int fizi_create(const fizi_geom *geom, const fizi_params *params, int32_t chunk_
         rc = c->ring.init(c->d + L.tables);
     if (rc == FIZI_OK) {
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->h_ring), sizeof(fizi_pointer) * kRing,
-                                     hipHostMallocDefault);
+                                     hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess)
+            e = hipHostGetDevicePointer(reinterpret_cast<void **>(&c->d_ring), c->h_ring, 0);
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&c->order_ev, kDeviceOrderEvent);
         for (int i = 0; i < kRecs && e == hipSuccess; ++i)
@@ -304,7 +291,7 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
     // pipelined calls, after the next call's first classify)
     const bool pipelined = c->pipe_calls || n_frames > c->chunk;
     int par = c->pipe_calls ? c->parity : 0;
-    int prev_join = c->pipe_calls ? c->pend_join : -1, last_slot = -1;
+    int prev_join = c->pipe_calls ? c->pend_join : -1;
     for (int f0 = 0; f0 < n_frames; f0 += c->chunk) {
         const int k = std::min(c->chunk, n_frames - f0);
         int slot;
@@ -333,11 +320,11 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
                 J.fizi = d_fizi_bits + f * words;
             J.hand = d_hand_bits ? d_hand_bits + f * words : nullptr;
             J.out = d_pointers ? d_pointers + f : internal + i;
+            J.hout = c->d_ring + (size_t)((fbase + (uint64_t)i) % kRing);
             J.frame_index = fbase + (uint64_t)i;
         }
         set_prefixes(T, k, c->tune);
-        const bool last = f0 + k == n_frames;
-        // the stream the chunk's back half and pointer copies go to
+        // the stream the chunk's back half goes to
         hipStream_t bs = s;
         if (pipelined) {
             FIZI_HIP(hipMemcpyAsync(c->ring.d[slot], &T, table_bytes(k), hipMemcpyHostToDevice, c->up));
@@ -354,8 +341,6 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
             FIZI_TRY(run_pipeline(c->ring.d[slot], T, k, k, (int)(W / 64), morph_ops(c->m.p), c->tune, c->n_cu,
                                   false, s, &c->clk));
         }
-        if (!d_pointers)
-            FIZI_TRY(copy_to_ring(c, internal, fbase, k, bs));
         FIZI_TRY(c->ring.finish(slot, bs));
         if (pipelined) {
             FIZI_HIP(hipEventRecord(c->join_ev[par], c->side));
@@ -366,40 +351,21 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
             prev_join = par;
             par ^= 1;
         }
-        last_slot = slot;
-        // the ring holds a chunk's pointers once its own copy is done
-        // (internal pointers) or once the call's single copy is done
-        if (!d_pointers) {
-            fizi_ctx::Rec &r = c->recs[c->next_rec];
-            c->next_rec = (c->next_rec + 1) % kRecs;
-            r.f0 = fbase;
-            r.f1 = fbase + k;
-            FIZI_HIP(hipEventRecord(r.ev, bs));
-            r.valid = true;
-        }
-        (void)last;
+        // the ring holds a chunk's pointers once its back half is done
+        fizi_ctx::Rec &r = c->recs[c->next_rec];
+        c->next_rec = (c->next_rec + 1) % kRecs;
+        r.f0 = fbase;
+        r.f1 = fbase + k;
+        FIZI_HIP(hipEventRecord(r.ev, bs));
+        r.valid = true;
     }
-    // the stream the call's single pointer copy goes to: after every back
-    // half of the call
-    hipStream_t cs = s;
     if (pipelined) {
         if (c->pipe_calls) {
             c->pend_join = prev_join;
             c->parity = par;
-            cs = c->side;
         } else {
             FIZI_HIP(hipStreamWaitEvent(s, c->join_ev[prev_join], 0));
         }
-    }
-    if (d_pointers) {
-        FIZI_TRY(copy_to_ring(c, d_pointers, c->next_frame, n_frames, cs));
-        FIZI_TRY(c->ring.finish(last_slot, cs));
-        fizi_ctx::Rec &r = c->recs[c->next_rec];
-        c->next_rec = (c->next_rec + 1) % kRecs;
-        r.f0 = c->next_frame;
-        r.f1 = c->next_frame + (uint64_t)n_frames;
-        FIZI_HIP(hipEventRecord(r.ev, cs));
-        r.valid = true;
     }
     c->next_frame += (uint64_t)n_frames;
     return mark_last(c, s);
@@ -414,7 +380,7 @@ int get_pointer(fizi_ctx *c, int64_t frame_index, fizi_pointer *h_out)
     if ((uint64_t)frame_index + kRing < c->next_frame)
         return fail(FIZI_ERANGE, "frame no longer kept (older than the last 65536)");
     // calls run in submission order, so the first recorded chunk that ends
-    // after the frame finishes no earlier than the frame's own copy
+    // after the frame finishes no earlier than the frame's own back half
     int best = -1;
     for (int i = 0; i < kRecs; ++i) {
         const fizi_ctx::Rec &r = c->recs[i];

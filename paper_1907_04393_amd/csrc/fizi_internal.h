@@ -70,6 +70,7 @@ struct Job {
     uint2 *runs;               // run_cap runs (first pixel, last pixel | link flag)
     uint2 *links;              // link_cap pairs of run starts to join
     fizi_pointer *out;         // one pointer
+    fizi_pointer *hout;        // its slot in a host ring (pinned, device-mapped), or null
     TrackState *track;         // the stream's tracking state, or null (largest component)
     uint64_t frame_index;
     int32_t W, H, Wd, rs;

@@ -1895,6 +1895,10 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
             }
         }
         *J->out = o;
+        // the final pointer also goes straight to the host ring, when the
+        // job has one (a deferred pick is settled by the chain kernel)
+        if (J->hout && !defer)
+            *J->hout = o;
     }
     __syncthreads();
 }
@@ -2025,8 +2029,11 @@ __global__ __launch_bounds__(kResolveThreads) void k_track_chain(Table *__restri
         __syncthreads();
     }
     // 3: the pointers and the stream's state
-    for (int j = threadIdx.x; j < nj; j += blockDim.x)
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) {
         *T->jobs[j].out = s_ptr[j];
+        if (T->jobs[j].hout)
+            *T->jobs[j].hout = s_ptr[j];
+    }
     if (threadIdx.x == 0) {
         ts->click = s_state;
         ts->valid = s_ax >= 0 ? 1 : 0;
