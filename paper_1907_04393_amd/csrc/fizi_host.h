@@ -135,15 +135,20 @@ int learn_model(Model &m, TableRing &ring, const Tuning &t, int n_cu, const uint
 // Enqueues gain, classify, morphology and components for the jobs of the
 // table in device memory. With fixed_grid the launch shapes do not depend on
 // the number of jobs (for graph capture); max_jobs bounds the resolve grid.
+// patch: a one-frame launch whose slot was not uploaded again (job 0's
+// per-call fields go with the gain launch, and the component stage zeroes
+// the job's accumulators after use, for the next such launch).
 int run_pipeline(const Table *d_tab, const Table &h, int njobs, int max_jobs, int max_wd, int max_ops,
-                 const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk);
+                 const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk,
+                 const CallPatch *patch = nullptr);
 // Its two halves: gain and classify (the front, which reads the frames and
 // writes the raw bits), then morphology and components (the back, which
 // reads the raw bits and writes I_FIZI and the pointers). beside: the back
 // half runs beside another step's front (smaller component workgroups).
 int run_front(const Table *d_tab, const Table &h, int njobs, const Tuning &t, int n_cu, bool fixed_grid,
-              hipStream_t s, StageClock *clk);
+              hipStream_t s, StageClock *clk, const CallPatch *patch = nullptr);
 int run_back(const Table *d_tab, const Table &h, int njobs, int max_jobs, int max_wd, int max_ops,
-             const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk, bool beside = false);
+             const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk, bool beside = false,
+             bool clear_acc = false);
 
 }  // namespace fizi

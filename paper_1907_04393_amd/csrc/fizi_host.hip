@@ -406,18 +406,19 @@ int learn_model(Model &m, TableRing &ring, const Tuning &t, int n_cu, const uint
 }
 
 int run_front(const Table *d_tab, const Table &h, int njobs, const Tuning &t, int n_cu, bool fixed_grid,
-              hipStream_t s, StageClock *clk)
+              hipStream_t s, StageClock *clk, const CallPatch *patch)
 {
     auto ev = [&](int st) { return clk ? clk->next(st) : StageEvents{}; };
     const int big = INT_MAX / 2;
-    FIZI_HIP(launch_gain(d_tab, fixed_grid ? big : h.h.gain_pre[njobs], n_cu, t, s, ev(FIZI_STAGE_GAIN)));
+    FIZI_HIP(launch_gain(d_tab, fixed_grid ? big : h.h.gain_pre[njobs], n_cu, t, s, ev(FIZI_STAGE_GAIN), patch));
     FIZI_HIP(launch_classify(d_tab, fixed_grid ? big : h.h.cls_pre[njobs], n_cu, t, s,
                              ev(FIZI_STAGE_CLASSIFY)));
     return FIZI_OK;
 }
 
 int run_back(const Table *d_tab, const Table &h, int njobs, int max_jobs, int max_wd, int max_ops,
-             const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk, bool beside)
+             const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk, bool beside,
+             bool clear_acc)
 {
     auto ev = [&](int st) { return clk ? clk->next(st) : StageEvents{}; };
     const int big = INT_MAX / 2;
@@ -425,15 +426,17 @@ int run_back(const Table *d_tab, const Table &h, int njobs, int max_jobs, int ma
                           ev(FIZI_STAGE_MORPH)));
     // tracked consecutive frames of one stream are resolved in order
     const bool serial = njobs > 1 && h.jobs[0].track != nullptr && h.jobs[1].track == h.jobs[0].track;
-    FIZI_HIP(launch_resolve(d_tab, fixed_grid ? max_jobs : njobs, s, ev(FIZI_STAGE_RESOLVE), serial, beside));
+    FIZI_HIP(launch_resolve(d_tab, fixed_grid ? max_jobs : njobs, s, ev(FIZI_STAGE_RESOLVE), serial, beside,
+                            clear_acc));
     return FIZI_OK;
 }
 
 int run_pipeline(const Table *d_tab, const Table &h, int njobs, int max_jobs, int max_wd, int max_ops,
-                 const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk)
+                 const Tuning &t, int n_cu, bool fixed_grid, hipStream_t s, StageClock *clk, const CallPatch *patch)
 {
-    FIZI_TRY(run_front(d_tab, h, njobs, t, n_cu, fixed_grid, s, clk));
-    return run_back(d_tab, h, njobs, max_jobs, max_wd, max_ops, t, n_cu, fixed_grid, s, clk);
+    FIZI_TRY(run_front(d_tab, h, njobs, t, n_cu, fixed_grid, s, clk, patch));
+    return run_back(d_tab, h, njobs, max_jobs, max_wd, max_ops, t, n_cu, fixed_grid, s, clk, false,
+                    patch != nullptr);
 }
 
 }  // namespace fizi

@@ -157,11 +157,23 @@ struct StageEvents {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, __VA_ARGS__);                \
     } while (0)
 
+// The per-call fields of job 0 of a one-frame launch, passed to the gain
+// kernel by value when the table slot on the device already holds the rest
+// of the job (valid != 0): the gain reads its frame from here, and its
+// first workgroup writes these fields into the job for the kernels after it.
+struct CallPatch {
+    const uint8_t *frame;
+    uint64_t *fizi, *hand;
+    fizi_pointer *out, *hout;
+    uint64_t frame_index;
+    int32_t valid;
+};
+
 // Kernel launchers (fizi_kernels.hip). Each returns the hipError_t of its launch.
 hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H, int rs,
                             hipStream_t s);
 hipError_t launch_gain(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t,
-                       hipStream_t s, StageEvents ev = {});
+                       hipStream_t s, StageEvents ev = {}, const CallPatch *patch = nullptr);
 hipError_t launch_minmax(const Table *d_tab, int njobs, uint8_t *bgmin, uint8_t *bgmax,
                          int npx, int reset, bool masked, int n_cu, hipStream_t s, StageEvents ev = {});
 hipError_t launch_classify(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t,
@@ -170,9 +182,10 @@ hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max
                         const Tuning &t, hipStream_t s, StageEvents ev = {});
 // serial: one workgroup takes the jobs in table order (consecutive frames of
 // one tracked stream); small: 256-thread workgroups, for a launch that runs
-// beside a streaming kernel.
+// beside a streaming kernel; clear_acc: each job's accumulators are zeroed
+// once read (its table slot is then reused without an upload).
 hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev = {}, bool serial = false,
-                          bool small = false);
+                          bool small = false, bool clear_acc = false);
 hipError_t launch_persistent(const Table *d_tab, int max_wd, int max_ops, int n_cu, const Tuning &t,
                              uint8_t *persist, hipStream_t s, StageEvents ev = {});
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);

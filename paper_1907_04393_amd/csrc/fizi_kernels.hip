@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_make_yref(const uint8_t *__restrict__ f
 // One sampled row of one frame: sums of reference and frame luminance over
 // its usable pixels, added to the frame's accumulators.
 template <int MODE>
-__device__ __forceinline__ void gain_tile_mode(Table *__restrict__ T, int j, int tile)
+__device__ __forceinline__ void gain_tile_mode(Table *__restrict__ T, int j, int tile, const uint8_t *fr)
 {
     __shared__ uint32_t s_num[256 / kWave], s_den[256 / kWave];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -276,11 +276,11 @@ __device__ __forceinline__ void gain_tile_mode(Table *__restrict__ T, int j, int
         num += ok ? y : 0u;
         den += ok ? r + 2 * gg + b : 0u;
     };
-    if ((reinterpret_cast<uintptr_t>(J->frame) & 15u) == 0) {
+    if ((reinterpret_cast<uintptr_t>(fr) & 15u) == 0) {
         // 16 pixels per item: three 16-byte loads of the frame row, two of
         // the reference row; items of the tile's rows in one flat range
         const int n16 = W / 16;
-        const GLOBAL uint8_t *frame = G(J->frame);
+        const GLOBAL uint8_t *frame = G(fr);
         const GLOBAL uint16_t *yref = G(J->yref);
         const size_t rowb = (size_t)J->rs * W * 3;
 #pragma unroll 2
@@ -307,7 +307,7 @@ __device__ __forceinline__ void gain_tile_mode(Table *__restrict__ T, int j, int
 #pragma unroll 4
     for (int it = threadIdx.x; it < nr * groups; it += blockDim.x) {
         const int rr = r0 + it / groups, g = it - (it / groups) * groups;
-        const GLOBAL uint32_t *row = G(reinterpret_cast<const uint32_t *>(J->frame + (size_t)rr * J->rs * W * 3));
+        const GLOBAL uint32_t *row = G(reinterpret_cast<const uint32_t *>(fr + (size_t)rr * J->rs * W * 3));
         const GLOBAL uint64_t *yr = G(reinterpret_cast<const uint64_t *>(J->yref + (size_t)rr * W));
         const uint32_t w0 = row[3 * g], w1 = row[3 * g + 1], w2 = row[3 * g + 2];
         const uint64_t yv = yr[g];
@@ -359,27 +359,42 @@ __device__ __forceinline__ void for_block_tiles(const int32_t *pre, int nj, F f)
 }
 
 // A gain tile, its hue test's case chosen once per tile.
-__device__ __forceinline__ void gain_tile(Table *__restrict__ T, int j, int tile)
+__device__ __forceinline__ void gain_tile(Table *__restrict__ T, int j, int tile, const uint8_t *fr)
 {
     switch (T->jobs[j].hue.mode) {
     case 0:
-        gain_tile_mode<0>(T, j, tile);
+        gain_tile_mode<0>(T, j, tile, fr);
         break;
     case 1:
-        gain_tile_mode<1>(T, j, tile);
+        gain_tile_mode<1>(T, j, tile, fr);
         break;
     case 2:
-        gain_tile_mode<2>(T, j, tile);
+        gain_tile_mode<2>(T, j, tile, fr);
         break;
     default:
-        gain_tile_mode<3>(T, j, tile);
+        gain_tile_mode<3>(T, j, tile, fr);
         break;
     }
 }
 
-__global__ __launch_bounds__(256) void k_gain(Table *__restrict__ T)
+// P.valid: job 0's per-call fields come with the launch (its table slot was
+// not uploaded again); the first workgroup stores them into the job for the
+// kernels that follow on the stream, and the tiles of job 0 take their frame
+// from P.
+__global__ __launch_bounds__(256) void k_gain(Table *__restrict__ T, CallPatch P)
 {
-    for_block_tiles(T->h.gain_pre, T->h.njobs, [&](int j, int tile) { gain_tile(T, j, tile); });
+    if (P.valid && blockIdx.x == 0 && threadIdx.x == 0) {
+        Job *J = &T->jobs[0];
+        J->frame = P.frame;
+        J->fizi = P.fizi;
+        J->hand = P.hand;
+        J->out = P.out;
+        J->hout = P.hout;
+        J->frame_index = P.frame_index;
+    }
+    for_block_tiles(T->h.gain_pre, T->h.njobs, [&](int j, int tile) {
+        gain_tile(T, j, tile, P.valid && j == 0 ? P.frame : T->jobs[j].frame);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -1903,13 +1918,27 @@ __device__ __forceinline__ void resolve_job(Table *__restrict__ T, int j, bool s
     __syncthreads();
 }
 
+// The job's accumulators (every field from the gain sums on) in 8-byte words.
+constexpr int kAccWords = (int)((sizeof(Job) - offsetof(Job, num)) / 8);
+static_assert((sizeof(Job) - offsetof(Job, num)) % 8 == 0 && offsetof(Job, num) % 8 == 0,
+              "the accumulators are whole 8-byte words");
+
 template <int NT>
-__global__ __launch_bounds__(NT) void k_resolve(Table *__restrict__ T, int defer)
+__global__ __launch_bounds__(NT) void k_resolve(Table *__restrict__ T, int defer, int clear_acc)
 {
+    static_assert(NT >= kAccWords, "one thread per accumulator word");
     __shared__ AreaTable s_tab;
     const int nj = T->h.njobs;
-    for (int j = blockIdx.x; j < nj; j += gridDim.x)
+    for (int j = blockIdx.x; j < nj; j += gridDim.x) {
         resolve_job(T, j, false, s_tab, defer != 0);
+        // clear_acc: zero the job's accumulators, as an upload of the table
+        // would, for a next call that reuses the slot without one. Every
+        // thread has read them (resolve_job ends on a barrier), and no later
+        // kernel of the call reads them.
+        if (clear_acc && threadIdx.x < kAccWords)
+            reinterpret_cast<unsigned long long *>(reinterpret_cast<uint8_t *>(&T->jobs[j]) +
+                                                   offsetof(Job, num))[threadIdx.x] = 0ull;
+    }
 }
 
 // Tracking of consecutive frames of one stream after a deferred component
@@ -2120,7 +2149,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX == 4 &
         const int seg = T->h.flow_seg[k], j = seg >> 1, idx = item - T->h.flow_pre[k];
         Job *J = &T->jobs[j];
         if ((seg & 1) == 0) {
-            gain_tile(T, j, idx);
+            gain_tile(T, j, idx, J->frame);
             const uint32_t ng = (uint32_t)(T->h.gain_pre[j + 1] - T->h.gain_pre[j]);
             if (publish_add(&J->gain_done, 1u, &s_u) + 1u == ng && threadIdx.x == 0) {
                 // the frame's last gain tile: its inverse gain, once, for every band
@@ -2199,12 +2228,15 @@ hipError_t launch_make_yref(const uint8_t *frame0, uint16_t *yref, int W, int H,
 }
 
 hipError_t launch_gain(const Table *d_tab, int total_tiles, int n_cu, const Tuning &t, hipStream_t s,
-                       StageEvents ev)
+                       StageEvents ev, const CallPatch *patch)
 {
     if (total_tiles <= 0)
         return hipSuccess;
     const int grid = min(total_tiles, n_cu * t.grid_per_cu);
-    FIZI_LAUNCH(k_gain, grid, 256, 0, s, ev, const_cast<Table *>(d_tab));
+    CallPatch p{};
+    if (patch)
+        p = *patch;
+    FIZI_LAUNCH(k_gain, grid, 256, 0, s, ev, const_cast<Table *>(d_tab), p);
     return hipGetLastError();
 }
 
@@ -2258,18 +2290,19 @@ hipError_t launch_morph(const Table *d_tab, int total_tiles, int max_wd, int max
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev, bool serial, bool small)
+hipError_t launch_resolve(const Table *d_tab, int njobs, hipStream_t s, StageEvents ev, bool serial, bool small,
+                          bool clear_acc)
 {
     if (njobs <= 0)
         return hipSuccess;
     // consecutive tracked frames of one stream: every frame's forest and
     // largest component at once, then the tracking chain in frame order
     Table *tab = const_cast<Table *>(d_tab);
-    const int defer = serial ? 1 : 0;
+    const int defer = serial ? 1 : 0, clear = clear_acc ? 1 : 0;
     if (small)
-        FIZI_LAUNCH(k_resolve<kResolveThreadsSmall>, njobs, kResolveThreadsSmall, 0, s, ev, tab, defer);
+        FIZI_LAUNCH(k_resolve<kResolveThreadsSmall>, njobs, kResolveThreadsSmall, 0, s, ev, tab, defer, clear);
     else
-        FIZI_LAUNCH(k_resolve<kResolveThreads>, njobs, kResolveThreads, 0, s, ev, tab, defer);
+        FIZI_LAUNCH(k_resolve<kResolveThreads>, njobs, kResolveThreads, 0, s, ev, tab, defer, clear);
     if (serial) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
