@@ -69,7 +69,10 @@ def _code_objects(blob: bytes):
 def kernel_hashes(lib_path: str = LIB) -> dict:
     """sha256 (first 16 hex digits) of every kernel's machine code and
     descriptor in the built library, keyed by symbol: measurements taken on
-    one build (HBM byte counters) are tied to the code they were taken on."""
+    one build (HBM byte counters) are tied to the code they were taken on.
+    The descriptor's code entry offset (bytes 16-23, the distance to where
+    the linker placed the code) is left out, so that a change to another
+    kernel of the library does not change the hash."""
     blob = open(lib_path, "rb").read()
     out = {}
     for co in _code_objects(blob):
@@ -96,8 +99,11 @@ def kernel_hashes(lib_path: str = LIB) -> dict:
                 continue
             start = sec[1] + (addr - sec[0])
             key = name[:-3] if name.endswith(".kd") else name
+            data = bytearray(co[start:start + size])
+            if name.endswith(".kd") and len(data) >= 24:
+                data[16:24] = bytes(8)
             h = out.setdefault(key, hashlib.sha256())
-            h.update(co[start:start + size])
+            h.update(bytes(data))
     return {k: v.hexdigest()[:16] for k, v in sorted(out.items())}
 
 
