@@ -54,7 +54,8 @@ TIMED_FORM = {0: 0, 1: 0, 2: 2, 3: 2, 4: 4, 5: 4}
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB -> 1 GiB
 # elementwise kernel gives), with the code hash of the kernel they were
 # taken on (the build writes lib/kernel_hashes.json)
-TRAFFIC = {"_ZN4fizi12_GLOBAL__N_110k_classifyILi8EEEvPNS_5TableE": ("d988ea94db2bced3", 1714.8e6)}
+TRAFFIC = {"_ZN4fizi12_GLOBAL__N_110k_classifyILi8EEEvPNS_5TableE": ("85c419a3c64feb26", 1714.7e6),
+           "_ZN4fizi12_GLOBAL__N_110k_classifyILi4EEEvPNS_5TableE": ("51db8709717845f7", 1714.4e6)}
 
 
 def log(*a):
@@ -115,7 +116,7 @@ def bench_batched(args, torch, fizi, workloads):
         c, r, g, m = (int(v) for v in args.shape.split(","))
         b.set_tuning(cls_iters=c, morph_rows=r, grid_per_cu=g, mode=m)
     elif not args.no_autotune:
-        best, ms = b.autotune(workloads.step_frames(w, 0), ptrs, steps=10, stream=stream)
+        best, ms = b.autotune(workloads.step_frames(w, 0), ptrs, steps=30, stream=stream)
         autotuned = {"picked": best, "ms_per_step": round(ms, 4)}
         log(f"autotuned launch shape {best}: {ms:.3f} ms/step")
     tuning = b.get_tuning()

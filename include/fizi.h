@@ -374,8 +374,11 @@ int fizi_batch_set_tuning(fizi_batch *b, const fizi_tuning *t);
  * frame steps of h_frames twice (as in fizi_batch_step, after two warm-up
  * steps) for each candidate of a coordinate sweep - mode, then cls_iters,
  * then grid_per_cu, then morph_rows - keeps the fastest by the better of its
- * two times, leaves it set, and returns it with its milliseconds per step.
- * Synchronous. */
+ * two times (a candidate replaces the current shape only when at least 1%
+ * faster, so that shapes within timing noise of each other leave it where
+ * it is; the sweep's pick is then timed against the starting shape three
+ * more times, in turn, and kept only if still 1% faster), leaves it set,
+ * and returns it with its milliseconds per step. Synchronous. */
 int fizi_batch_autotune(fizi_batch *b, const uint8_t *const *h_frames, fizi_pointer *d_pointers,
                         int32_t steps, void *stream, fizi_tuning *best, double *best_ms);
 

@@ -115,10 +115,12 @@ Tuning tuning_for(int max_width, int max_ops, bool batch)
     t.cls_iters = 4;
     if (batch) {
         // the autotuner's pick on the 64-stream 640x480..3840x2160 workload
-        // in the pipelined launch mode: 16-row bands and a grid of 64 blocks
-        // per CU for the streaming kernels (eight rounds of resident blocks
-        // even out the tail, and leave slots free often enough for the back
-        // half that runs beside them)
+        // in the pipelined launch mode: 8 pixel groups per classify lane,
+        // 16-row bands and a grid of 64 blocks per CU for the streaming
+        // kernels (eight rounds of resident blocks even out the tail, and
+        // leave slots free often enough for the back half that runs beside
+        // them)
+        t.cls_iters = 8;
         t.grid_per_cu = 64;
         t.morph_rows = 16;
     } else {
