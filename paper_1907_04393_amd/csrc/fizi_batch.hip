@@ -56,10 +56,10 @@ struct BatchLayout {
 };
 
 bool is_pipelined(int mode) { return mode == FIZI_BATCH_PIPELINED || mode == FIZI_BATCH_PIPELINED_GRAPH; }
+bool is_persistent(int mode) { return mode == FIZI_BATCH_PERSISTENT || mode == FIZI_BATCH_PERSISTENT_GRAPH; }
 
 // How much faster than the current shape an autotuner candidate must be.
 constexpr double kTuneMargin = 0.01;
-bool is_persistent(int mode) { return mode == FIZI_BATCH_PERSISTENT || mode == FIZI_BATCH_PERSISTENT_GRAPH; }
 
 int check_streams(int32_t n, const fizi_geom *geoms, const fizi_params *params)
 {
@@ -454,8 +454,8 @@ int fizi_batch_step(fizi_batch *b, const uint8_t *const *h_frames, uint64_t *con
     for (int i = 0; i < b->n; ++i)
         if (h_frames[i])
             short_waves += (size_t)((b->m[i].g.height + kShortBand - 1) / kShortBand);
-    const bool short_chain = b->tune.short_bands && b->mode != FIZI_BATCH_PERSISTENT &&
-                             b->mode != FIZI_BATCH_PERSISTENT_GRAPH && short_waves <= (size_t)b->n_cu * 4;
+    const bool short_chain =
+        b->tune.short_bands && !is_persistent(b->mode) && short_waves <= (size_t)b->n_cu * 4;
     int k = 0;
     for (int i = 0; i < b->n; ++i) {
         if (!h_frames[i])

@@ -386,13 +386,17 @@ int process_frames(fizi_ctx *c, const uint8_t *d_frames, int32_t n_frames, uint6
             const Job &J = T.jobs[0];
             const CallPatch P{J.frame, J.fizi, J.hand, J.out, J.hout, J.frame_index, 1};
             const OneJobKey key = one_job_key(T);
-            if (c->shadow_gen[slot] != c->gen || std::memcmp(&c->shadow[slot], &key, sizeof(key)) != 0) {
+            const bool reuse =
+                c->shadow_gen[slot] == c->gen && std::memcmp(&c->shadow[slot], &key, sizeof(key)) == 0;
+            // stale until every kernel of this call is enqueued (a launch
+            // that fails leaves the slot to a full upload next time)
+            c->shadow_gen[slot] = 0;
+            if (!reuse)
                 FIZI_HIP(hipMemcpyAsync(c->ring.d[slot], &T, table_bytes(1), hipMemcpyHostToDevice, s));
-                c->shadow[slot] = key;
-                c->shadow_gen[slot] = c->gen;
-            }
             FIZI_TRY(run_pipeline(c->ring.d[slot], T, k, k, (int)(W / 64), morph_ops(c->m.p), c->tune, c->n_cu,
                                   false, s, &c->clk, &P));
+            c->shadow[slot] = key;
+            c->shadow_gen[slot] = c->gen;
         } else {
             c->shadow_gen[slot] = 0;
             FIZI_HIP(hipMemcpyAsync(c->ring.d[slot], &T, table_bytes(k), hipMemcpyHostToDevice, s));
