@@ -204,7 +204,7 @@ def bench_plain(args, torch, fizi, scene):
     ctx.set_pipelined(True)
     stream = torch.cuda.current_stream()
     ptrs = torch.empty((args.plain_batch, 56), dtype=torch.uint8, device=dev)
-    for _ in range(2):
+    for _ in range(6):
         ctx.process_into(pool, args.plain_batch, pointers=ptrs, stream=stream)
     ctx.flush(stream)
     torch.cuda.synchronize()
