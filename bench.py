@@ -279,13 +279,18 @@ def bench_learn(args, torch, fizi, scene):
     ctx = fizi.Context(W, H, chunk=1, device=dev)
     ctx.learn_background(bg)
     torch.cuda.synchronize()
-    ctx.stage_timing(True)
+    # wall time per call with the stage clock off (its events cost more
+    # than a call), then the kernel's own time from its dispatch events
     reps = 5
     t0 = time.perf_counter()
     for _ in range(reps):
         ctx.learn_background(bg)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
+    ctx.stage_timing(True)
+    for _ in range(reps):
+        ctx.learn_background(bg)
+    torch.cuda.synchronize()
     ms, launches = ctx.stage_times()["learn"]
     k_s = ms / 1e3 / max(1, launches)
     byts = W * H * (3 * n + 12)
@@ -295,19 +300,23 @@ def bench_learn(args, torch, fizi, scene):
     # partial re-learning: running frames fed back with their I_FIZI masks
     # (model 12 B/px once per call, each frame 3 B/px + its mask 1/8 B/px)
     hand = scene.Scene(spec, device=dev).hand_frames(0, 8)
+    ctx.stage_timing(False)
     bits = ctx.process_frames(hand, want_fizi=True)["fizi"]
     torch.cuda.synchronize()
-    ctx.stage_times()
     for k in (1, 8):
         ctx.relearn_background(hand[:k], bits[:k])
         torch.cuda.synchronize()
-        ctx.stage_times()
         t0 = time.perf_counter()
         for _ in range(reps):
             ctx.relearn_background(hand[:k], bits[:k])
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / reps
+        ctx.stage_timing(True)
+        for _ in range(reps):
+            ctx.relearn_background(hand[:k], bits[:k])
+        torch.cuda.synchronize()
         ms, launches = ctx.stage_times()["learn"]
+        ctx.stage_timing(False)
         k_s = ms / 1e3 / max(1, launches)
         byts = W * H * ((3 + 1 / 8) * k + 12)
         out[f"relearn_{k}_frames"] = {"ms_per_call": round(sec * 1e3, 3), "kernel_us": round(k_s * 1e6, 1),
