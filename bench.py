@@ -349,13 +349,18 @@ def bench_soft(args, torch, scene):
                                  ("fused_bce", lambda: soft.soft_bce(f, gt, prm, 0.5), 4, "backward")):
         fn()
         torch.cuda.synchronize()
-        soft.times()
-        soft.timing(True)
+        # the call's wall time with the dispatch events off, then the
+        # kernels' own times from their events
         t0 = time.perf_counter()
         for _ in range(reps):
             fn()
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / reps
+        soft.times()
+        soft.timing(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
         tm = soft.times()
         soft.timing(False)
         k_s = tm[stage][0] / 1e3 / max(1, tm[stage][1])
