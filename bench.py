@@ -496,8 +496,8 @@ def cpu_baseline(args, scene, w):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--pool", type=int, default=4, help="resident hand frames per stream")
     ap.add_argument("--latency-steps", type=int, default=50)
     ap.add_argument("--plain-batch", type=int, default=256)
