@@ -71,3 +71,57 @@ def test_null_arguments_are_errors():
     assert L.process_frames(None, None, 1, None, None, None, None) == fizi.FIZI_EINVAL
     assert L.get_pointer(None, 0, None) == fizi.FIZI_EINVAL
     assert L.fizi_destroy(None) == 0
+
+
+def test_setters_reject_null_handles():
+    """The context's and the batch's setters refuse a null handle before any
+    device work."""
+    from paper_1907_04393_amd import fizi
+    L = fizi.lib()
+    assert L.fizi_set_short_bands(None, 1) == fizi.FIZI_EINVAL
+    assert L.fizi_set_pipelined(None, 1) == fizi.FIZI_EINVAL
+    assert L.fizi_set_tracking(None, 1) == fizi.FIZI_EINVAL
+    assert L.fizi_flush(None, None) == fizi.FIZI_EINVAL
+    t = fizi.Tuning()
+    assert L.fizi_batch_get_tuning(None, ctypes.byref(t)) == fizi.FIZI_EINVAL
+    assert L.fizi_batch_set_tuning(None, ctypes.byref(t)) == fizi.FIZI_EINVAL
+
+
+_CTYPES = {"int32_t": ctypes.c_int32, "uint8_t": ctypes.c_uint8, "uint16_t": ctypes.c_uint16,
+           "uint32_t": ctypes.c_uint32, "uint64_t": ctypes.c_uint64}
+
+
+def _c_structs():
+    """Fields (name, ctypes type) of every plain typedef struct in
+    include/fizi.h, in declaration order."""
+    txt = open(os.path.join(ROOT, "include", "fizi.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for m in re.finditer(r"typedef\s+struct\s*\{(.*?)\}\s*([a-z_0-9]+)\s*;", txt, flags=re.S):
+        fields = []
+        for decl in m.group(1).split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            ty, names = decl.split(None, 1)
+            fields += [(n.strip(), _CTYPES[ty]) for n in names.split(",")]
+        out[m.group(2)] = fields
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("fizi_geom", "Geom"), ("fizi_params", "Params"),
+                                          ("fizi_pointer", "PointerC"), ("fizi_layout", "Layout"),
+                                          ("fizi_tuning", "Tuning"), ("fizi_zone", "ZoneC"),
+                                          ("fizi_wheel", "WheelC")])
+def test_binding_structs_mirror_the_header(cname, pyname):
+    """Every struct the binding passes by pointer has the header's fields, in
+    order and width, so that the two sides agree on the layout."""
+    from paper_1907_04393_amd import fizi
+    py = [(n, t) for n, t in getattr(fizi, pyname)._fields_]
+    assert py == _c_structs()[cname], cname
+    assert ctypes.sizeof(getattr(fizi, pyname)) == sum(ctypes.sizeof(t) for _, t in py)
+
+
+def test_drive_fields_mirror_the_header():
+    from paper_1907_04393_amd import fizi
+    assert tuple(n for n, _ in _c_structs()["fizi_drive"]) == fizi.DRIVE_FIELDS
