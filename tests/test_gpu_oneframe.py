@@ -96,3 +96,35 @@ def test_one_frame_calls_match_oracle():
     one_frame_calls(9, "tracked, 8-row bands")
     assert st["next"] == 64
     ctx.close()
+
+
+@pytest.mark.parametrize("track", [False, True])
+def test_one_frame_calls_on_two_streams(track):
+    """Back-to-back one-frame calls alternating between two streams, outputs
+    read once at the end: each call is ordered after the previous one (whose
+    component stage zeroed the accumulators its slot's next call relies on)
+    whatever stream it comes on."""
+    from oracle import oracle
+    from paper_1907_04393_amd import fizi
+    dev = need_gpu()
+    bg, _, hand = _scene()
+    hd = hand.to(dev)
+    ctx = fizi.Context(W, H, chunk=4, device=dev)
+    ctx.learn_background(bg.to(dev))
+    ctx.set_tracking(track)
+    m = oracle.Model(W, H)
+    m.learn(bg.numpy())
+    t = oracle.Tracker(m) if track else None
+    streams = [torch.cuda.current_stream(dev), torch.cuda.Stream(device=dev)]
+    streams[1].wait_stream(streams[0])
+    outs = []
+    for i in range(20):
+        s = streams[i % 2]
+        with torch.cuda.stream(s):
+            outs.append(ctx.process_frames(hd[i:i + 1].contiguous(), want_fizi=True, stream=s))
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        r = t.process(hand[i].numpy(), frame_index=i) if t else m.process(hand[i].numpy(), frame_index=i)
+        assert fizi.pointer_dict(fizi.pointers_to_numpy(o["pointers"])[0]) == r["pointer"], (track, i)
+        assert np.array_equal(fizi.unpack_bits(o["fizi"], W)[0], r["fizi"]), (track, i)
+    ctx.close()
